@@ -1,0 +1,99 @@
+"""Pins for the oracle's costs, path-integral weights, update and validation (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_29663_amd import scenes
+
+
+PRM = dict(scenes.COST_DEFAULTS, goal=(1.0, -2.0), nu=2)
+
+
+def test_phi_obs_hand_values(orc):
+    ds, wc, wr = 0.05, 1e3, 1e2
+    cases = {-0.1: wc + wr * 0.15 ** 2, 0.0: wr * ds ** 2, -0.0: wr * ds ** 2,
+             ds / 2: wr * (ds / 2) ** 2, ds: 0.0, 1.0: 0.0, math.inf: 0.0}
+    for d, want in cases.items():
+        assert orc.phi_obs(PRM, d) == pytest.approx(want, rel=1e-6, abs=1e-12), d
+
+
+def test_costs_hand_computed(orc):
+    """Two rollouts, two steps: every term written out by hand."""
+    xy = np.array([[[1.0, -2.0], [4.0, 2.0]], [[0.0, 0.0], [1.0, -1.0]]])
+    u = np.array([[[1.0, 2.0], [0.0, -1.0]], [[0.5, 0.5], [0.0, 0.0]]])
+    d = np.array([[1.0, 0.02], [-0.01, math.inf]])
+    J, chi, Jt = orc.costs(PRM, xy, u, d)
+    f32 = lambda v: float(np.float32(v))
+    w_rep, w_coll, w_inf, ds, wct = f32(1e2), f32(1e3), f32(1e4), f32(0.05), f32(0.1)
+    j0 = (0 + wct * (1 + 4) + 0) + (5 + wct * 1 + w_rep * (ds - 0.02) ** 2)
+    j1 = (math.hypot(1, 2) + wct * 0.5 + w_coll + w_rep * (ds + 0.01) ** 2) + (1 + 0 + 0)
+    np.testing.assert_allclose(J, [j0, j1], rtol=1e-12)
+    assert list(chi) == [True, True]
+    np.testing.assert_allclose(Jt, [j0 + w_inf, j1 + w_inf], rtol=1e-12)
+    _, chi2, Jt2 = orc.costs(PRM, xy[:1, :1], u[:1, :1], d[:1, :1])
+    assert not chi2[0] and Jt2[0] == pytest.approx(wct * 5)
+
+
+def test_weights_properties(orc):
+    rng = np.random.default_rng(0)
+    J = rng.uniform(0, 20, 100)
+    w = orc.weights(J, 1.0)
+    assert w.sum() == pytest.approx(1.0) and np.all(w > 0)
+    assert w.argmax() == J.argmin()
+    np.testing.assert_allclose(orc.weights(J + 123.0, 1.0), w, rtol=1e-12)      # shift invariance
+    np.testing.assert_allclose(orc.weights(np.full(7, 3.3), 1.0), np.full(7, 1 / 7))
+    np.testing.assert_allclose(orc.weights(J, 1e12), np.full(100, 0.01), rtol=1e-9)  # lambda -> inf
+    w0 = orc.weights(J, 1e-6)                                                  # lambda -> 0
+    assert w0[J.argmin()] == pytest.approx(1.0) and np.sort(w0)[-2] < 1e-12
+    J2 = np.array([1.3, 2.9])
+    assert orc.weights(J2, 0.7)[0] == pytest.approx(1 / (1 + math.exp(-(2.9 - 1.3) / 0.7)))
+
+
+def test_update_properties(orc):
+    rng = np.random.default_rng(1)
+    K, T, nu = 9, 6, 3
+    eps = rng.normal(size=(K, T, nu))
+    U = rng.normal(size=(T, nu))
+    np.testing.assert_allclose(orc.update(U, np.array([1.0]), eps[:1]), U + eps[0])  # K = 1
+    np.testing.assert_allclose(orc.update(U, np.full(K, 1 / K), eps), U + eps.mean(0))
+    w = orc.weights(rng.uniform(0, 5, K), 1.0)
+    np.testing.assert_allclose(orc.update(U, w, eps), U + np.einsum("k,kth->th", w, eps))
+
+
+def test_validate_shift(orc):
+    U = np.arange(8.0).reshape(4, 2)
+    ok, us, Un = orc.validate_shift(U, np.array([1.0, 0.5, np.inf, 0.06]), 0.05)
+    assert ok and list(us) == [0.0, 1.0]
+    np.testing.assert_array_equal(Un, [[2, 3], [4, 5], [6, 7], [6, 7]])
+    ok, us, Un = orc.validate_shift(U, np.array([1.0, 0.049, 1.0, 1.0]), 0.05)
+    assert not ok and list(us) == [0.0, 0.0] and np.all(Un == 0)
+    ok, _, _ = orc.validate_shift(U, np.array([1.0, np.nan, 1.0, 1.0]), 0.05)
+    assert not ok
+
+
+def test_step_validation_forces_hold_and_reset(orc):
+    """Points placed on the nominal path force a zero-velocity hold and a reset;
+    with every point masked the nominal is always valid."""
+    prm = scenes.params("c1", K=32, T=10, sigma=(1e-3, 1e-3))
+    U = np.tile(np.float32([1.0, 0.0]), (prm["T"], 1))
+    scene = dict(ox=np.float32([1.0, 0.5]), oy=np.float32([0.0, 0.0]), polygon=scenes.FOOTPRINT_L8)
+    out = orc.mppi_step(prm, np.zeros(3, np.float32), U, scene, 1, 0)
+    assert not out["valid"] and np.all(out["u_star"] == 0) and np.all(out["U_next"] == 0)
+    scene["valid"] = np.zeros(2, np.uint8)
+    out = orc.mppi_step(prm, np.zeros(3, np.float32), U, scene, 1, 0)
+    assert out["valid"] and np.all(np.isinf(out["d"]))
+    np.testing.assert_allclose(out["u_star"], out["U_upd"][0])
+    np.testing.assert_allclose(out["U_next"][:-1], out["U_upd"][1:])
+
+
+def test_step_moves_towards_goal(orc):
+    """Open-field sanity: with no obstacles, repeated steps drive the nominal
+    forward towards a goal straight ahead."""
+    prm = scenes.params("c1", K=256, T=20, goal=(3.0, 0.0))
+    scene = dict(ox=np.float32([50.0]), oy=np.float32([50.0]), polygon=scenes.FOOTPRINT_L8)
+    U = np.zeros((prm["T"], 2), np.float32)
+    for step in range(6):
+        out = orc.mppi_step(prm, np.zeros(3, np.float32), U, scene, 5, step)
+        U = out["U_next"].astype(np.float32)
+    assert U[:5, 0].mean() > 0.3
