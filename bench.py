@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of one MPPI control step with exact footprint signed distance.
+
+A step is one pass of Algorithm 1 (sampling, rollouts, rollout-frame
+transform, exact polygon signed distance, masked min over points, costs,
+softmax update, nominal re-rollout and validation) on the Ackermann corridor
+workload: K = 2048 rollouts, T = 40 steps, N = 8192 obstacle points, 16-vertex
+non-convex footprint, FP32 on the GPU.
+
+Prints ONE JSON line.  `value` is SDF evaluations per second of the whole step
+(point-edge pairs of the sampled rollouts plus the validation pass, divided by
+the step's wall time); `ms_per_step` is the step latency.  `roofline` reports
+the dominant kernel (fused transform + signed distance + min) against the
+VALU issue peak, timed with HIP events recorded on the library's stream
+around every launch of that kernel in the timed region.  `cpu_baseline` is the
+CPU oracle timed on a bounded sample of the same step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one wave64 VALU instruction per CU per clock.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Minimal VALU lane-instructions per unit of work (derivation in the design doc):
+#   polygon: 12 per (pose, point, edge) + 4 per (pose, point)
+#   rectangle cover: 10 per (pose, point, box) + 7 per (pose, point)
+OPS = {0: (12.0, 4.0), 1: (10.0, 7.0)}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rollouts", type=int, default=768,
+                    help="rollouts in the oracle's bounded sample of the step")
+    return ap.parse_args()
+
+
+def traffic_record(kernel_src, workload):
+    """HBM bytes per launch measured by rocprofv3 counters, if they were taken on
+    the current source of the kernel (sha256 recorded next to the numbers)."""
+    path = os.path.join(ROOT, "profiles", f"dmin_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if rec.get("kernel_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                                   "described in DESIGN.md and not implemented",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2605_29663_amd as pkg
+    from paper_2605_29663_amd import scenes
+
+    prm, sc = scenes.config(args.config)
+    kind = prm["footprint_kind"]
+    K, T, nu = prm["K"], prm["T"], prm["nu"]
+    N = int(np.size(sc["ox"]))
+    geom = sc["polygon"] if kind == 0 else sc["rects"]
+    P = len(geom)
+
+    ctx = pkg.Context(0)
+    ctx.set_footprint(kind, geom)
+    ctx.set_points(sc["ox"], sc["oy"], sc.get("ovx"), sc.get("ovy"), sc.get("valid"))
+    U = torch.zeros((T, nu), dtype=torch.float32, device="cuda")
+    params = pkg.make_params(prm)
+    q0 = (0.0, 0.0, 0.0)
+    seed = 0x5EED0002
+
+    for i in range(args.warmup):
+        ctx.mppi_step(None, q0, U, seed, i, params=params)
+    torch.cuda.synchronize()
+    ctx.mppi_set_profiling(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        ctx.mppi_step(None, q0, U, seed, args.warmup + i, params=params)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n = ctx.mppi_get_profile()
+    ctx.mppi_set_profiling(False)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    pairs_main = K * T * N * P
+    pairs_step = pairs_main + (T * N * P if prm["validate"] else 0)
+    value = pairs_step / (ms_step / 1e3)
+    per_unit, per_pose_point = OPS[kind]
+    ops_launch = pairs_main * per_unit + K * T * N * per_pose_point
+    k_avg_ms = k_ms / max(k_n, 1)
+    achieved = ops_launch / (k_avg_ms / 1e3) / 1e12
+    kernel_src = os.path.join(ROOT, "paper_2605_29663_amd", "csrc", "kernels_sdf.hip")
+    workload = args.config
+
+    out = {
+        "metric": "SDF evals/s (K*T*N*edges per MPPI step) and MPPI step latency",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p95": float(np.percentile(lat, 95) * 1e3)},
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded scene generator)",
+        "config": {"workload": {"c1": "unicycle open field", "c2": "ackermann corridor",
+                                "c3": "omni rectangle cover, moving points"}[args.config],
+                   "K": K, "T": T, "N": N, ("B" if kind == 0 else "R"): P,
+                   "motion_model": prm["model"], "dt": prm["dt"]},
+        "roofline": {"bound": "alu", "kernel": "k_dmin_poly" if kind == 0 else "k_dmin_rect",
+                     "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": traffic_record(kernel_src, workload),
+                     "kernel_ms": k_avg_ms, "launches": k_n},
+    }
+
+    if not args.no_cpu_baseline:
+        sys.path.insert(0, ROOT)
+        from oracle import oracle as orc
+        Ks = min(args.cpu_rollouts, K)
+        prm_s = dict(prm, K=Ks)
+        ts = time.perf_counter()
+        orc.mppi_step(prm_s, np.zeros(3, np.float32), np.zeros((T, nu), np.float32), sc, seed, 0)
+        cpu_s = time.perf_counter() - ts
+        cpu_pairs = (Ks * T + (T if prm["validate"] else 0)) * N * P
+        out["cpu_baseline"] = {"value": cpu_pairs / cpu_s, "unit": "evals/s",
+                               "cores": orc.num_threads(), "kind": "oracle",
+                               "sample": f"whole oracle step with {Ks} of {K} rollouts "
+                                         f"(full T={T}, N={N}, {P} primitives), {cpu_s:.1f} s"}
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * exact_mppi.h -- C ABI of the MI355X (gfx950) library for one MPPI control
+ * step with exact footprint signed distance.
+ *
+ * Paper: "EXACT-MPPI" (arXiv 2605.29663).  Section and equation names below
+ * refer to that paper.
+ *
+ * Conventions for every entry point
+ *   - Return value: MPPI_OK (0) on success, a negative MPPI_E_* code on
+ *     failure.  mppi_last_error(ctx) then holds a human-readable message.
+ *     On failure no output is guaranteed to be written.
+ *   - Pointers whose name starts with "d" (dposes, dU, ...) are DEVICE
+ *     pointers on the context's device; every other pointer is host memory.
+ *   - The caller owns every pointer it passes; the library copies whatever
+ *     it keeps (footprint, points) into buffers it owns.
+ *   - All device work is ordered on the context's stream.  Calls return
+ *     without waiting for the GPU, except where "synchronous" is stated.
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ *   - Floating point is IEEE binary32 on the device.
+ */
+#ifndef EXACT_MPPI_H
+#define EXACT_MPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPPI_API __attribute__((visibility("default")))
+
+enum {
+    MPPI_OK = 0,
+    MPPI_E_ARG = -1,          /* invalid argument (NULL, negative size, bad enum) */
+    MPPI_E_FOOTPRINT = -2,    /* footprint rejected (not simple, degenerate, non-finite) */
+    MPPI_E_NO_FOOTPRINT = -3, /* the requested footprint kind was never set */
+    MPPI_E_CAPACITY = -4,     /* size outside the supported range */
+    MPPI_E_HIP = -5,          /* a HIP runtime call failed (message has hipGetErrorString) */
+    MPPI_E_STATE = -6         /* call order violated (e.g. no points set) */
+};
+
+enum { MPPI_FP_POLYGON = 0, MPPI_FP_RECTS = 1 };
+
+/* Motion models, Section "Robot Kinematic Models".  Controls per model:
+ *   UNICYCLE  (v, omega)          nu = 2
+ *   ACKERMANN (v, delta), wheelbase L     nu = 2
+ *   OMNI      (v_x, v_y, omega)   nu = 3
+ *   SPIN      (omega)             nu = 1
+ *   PARALLEL  (v_para)            nu = 1                                     */
+enum { MPPI_UNICYCLE = 0, MPPI_ACKERMANN = 1, MPPI_OMNI = 2, MPPI_SPIN = 3, MPPI_PARALLEL = 4 };
+
+/* Capacities. */
+#define MPPI_MAX_B 32        /* polygon vertices */
+#define MPPI_MAX_R 32        /* rectangles in a cover */
+#define MPPI_MAX_T 128       /* horizon */
+#define MPPI_MAX_K (1 << 20) /* rollouts */
+
+typedef struct mppi_ctx_s* mppi_ctx;
+
+/* Parameters of one control cycle (Algorithm 1 "Params", plus the cost
+ * forms the paper leaves open).  Field by field:
+ *   K, T, nu, model   rollouts, horizon, control width, MPPI_* model
+ *   footprint_kind    MPPI_FP_POLYGON or MPPI_FP_RECTS (Section
+ *                     "Computational Footprint Representations")
+ *   dt, lambda        Euler step and softmax temperature
+ *   wheelbase         L of the Ackermann model
+ *   sigma[c]          standard deviation of the Gaussian perturbation of
+ *                     control channel c
+ *   u_min, u_max      box the sampled control is clipped to; the update uses
+ *                     the clipped perturbation eps_eff = u - U_h
+ *   d_safe, w_coll, w_rep, w_inf   obstacle penalty, unsafe flag and
+ *                     augmented cost (Section "Safety Penalties and
+ *                     Trajectory Validation")
+ *   w_goal, goal[2]   task term w_goal * |(x, y) - goal|
+ *   w_ctrl[c]         control term sum_c w_ctrl[c] u_c^2
+ *   state_offset      1: the (r, h) term scores the post-step state q_{h+1}
+ *                     (moving points at time (h+1) dt); 0: the pre-step q_h
+ *   validate          1: run Algorithm 1 step 4 (nominal re-rollout,
+ *                     d >= d_safe check, hold-and-reset on failure);
+ *                     0: always execute U_0 and shift                       */
+typedef struct mppi_params {
+    int32_t K, T, nu, model, footprint_kind;
+    float dt, lambda, wheelbase;
+    float sigma[3], u_min[3], u_max[3];
+    float d_safe, w_coll, w_rep, w_inf, w_goal, w_ctrl[3];
+    float goal[2];
+    int32_t state_offset;
+    int32_t validate;
+} mppi_params;
+
+/* Optional device outputs of mppi_step; any pointer may be NULL.
+ *   d_min   K*T, row-major [r][h]: minimum signed distance over points
+ *   argmin  K*T: caller's index of the point attaining d_min (-1 if none)
+ *   J       K: augmented cost J~
+ *   w       K: normalised weights omega
+ *   poses   K*T*4: scored pose (x, y, cos theta, sin theta)
+ *   eps     K*T*nu: clipped perturbation eps_eff
+ *   u       K*T*nu: sampled (clipped) control
+ *   U_upd   T*nu: nominal after the weighted update, before validation
+ *   d_nom   T: minimum signed distance along the updated nominal          */
+typedef struct mppi_diag {
+    float* d_min;
+    int32_t* argmin;
+    float* J;
+    float* w;
+    float* poses;
+    float* eps;
+    float* u;
+    float* U_upd;
+    float* d_nom;
+} mppi_diag;
+
+/* Create a context on HIP device `device`; work is issued on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  *out receives the
+ * handle.  Errors: MPPI_E_ARG, MPPI_E_HIP.                                   */
+MPPI_API int mppi_create(mppi_ctx* out, int device, void* hip_stream);
+
+/* Release every buffer of the context (synchronises its stream). */
+MPPI_API int mppi_destroy(mppi_ctx ctx);
+
+/* Message of the last failed call on ctx (ctx may be NULL for failures of
+ * mppi_create).  The string stays valid until the next call on ctx.          */
+MPPI_API const char* mppi_last_error(mppi_ctx ctx);
+
+/* Set the effective footprint (Section "Computational Footprint
+ * Representations").  host points to host memory:
+ *   MPPI_FP_POLYGON: count = B vertices, x0,y0,x1,y1,... (2B floats), the
+ *     ordered cyclic vertex list of a simple polygon, either orientation,
+ *     3 <= B <= MPPI_MAX_B.  Rejected (MPPI_E_FOOTPRINT): a non-finite
+ *     value, a zero-length edge, |area| < 1e-12 m^2, or two non-adjacent
+ *     edges that touch or cross.  Collinear vertices are allowed.
+ *   MPPI_FP_RECTS: count = R rectangles, (c_x, c_y, s_x, s_y) each (4R
+ *     floats; centre and half extents, Section "Orthogonal Footprints via
+ *     Rectangle Covering"), 1 <= R <= MPPI_MAX_R, s_x, s_y > 0, finite.
+ * Both kinds may be set; mppi_params.footprint_kind picks one per step.
+ * The data are copied; the call is synchronous.                             */
+MPPI_API int set_footprint(mppi_ctx ctx, int kind, const float* host, int count);
+
+/* Host-only check of a footprint description, with the rules of
+ * set_footprint (no device work, no context).  On rejection the reason is
+ * written to msg (host buffer of msg_len bytes, may be NULL).  Returns
+ * MPPI_OK, MPPI_E_FOOTPRINT, MPPI_E_CAPACITY or MPPI_E_ARG.                 */
+MPPI_API int mppi_check_footprint(int kind, const float* host, int count, char* msg, int msg_len);
+
+/* Set the obstacle set O = {o_i} (Section "Robot--Obstacle Signed
+ * Distance") as device structure-of-arrays of n points in the planning
+ * frame.  dvx, dvy (may be NULL: static points) give a constant velocity
+ * per point; the point at time t is o_i + v_i t.  dvalid (may be NULL: all
+ * valid) is the validity mask of Section "Batched Rollout and Distance
+ * Computation": masked points never contribute.  Points with a non-finite
+ * coordinate or velocity are treated as masked.  n may be 0.  The data are
+ * copied (stream-ordered) into library buffers, so the caller may reuse its
+ * arrays once the stream has passed this call.                              */
+MPPI_API int set_points(mppi_ctx ctx, const float* dx, const float* dy, const float* dvx,
+               const float* dvy, const unsigned char* dvalid, int n);
+
+/* Signed distance of n body-frame query points to the polygon footprint:
+ * d = sigma(p) min_b d_seg,b(p) (Section "Distance to General Simple
+ * Polygonal Footprint"; sign from the crossing-number test).  dpx, dpy, dd:
+ * device arrays of n floats.  Negative inside, positive outside.           */
+MPPI_API int sdf_polygon(mppi_ctx ctx, const float* dpx, const float* dpy, int n, float* dd);
+
+/* Signed distance of n body-frame points to the rectangle cover:
+ * d = min_j ( |max(a_j, 0)| + min(max(a_jx, a_jy), 0) ), a_j = |p - c_j| - s_j
+ * (Section "Distance to Orthogonal Footprints").  Same layout as above.     */
+MPPI_API int sdf_rectcover(mppi_ctx ctx, const float* dpx, const float* dpy, int n, float* dd);
+
+/* Minimum signed-distance matrix for given poses (Section "Batched Rollout
+ * and Distance Computation"; Algorithm 1 step 2): for each of the K*T poses
+ * (device float4 (x, y, cos theta, sin theta), row-major [r][h]) every valid
+ * point is moved to time (h + state_offset) dt, transformed into that pose's
+ * body frame (Section "Rollout-Frame Transformation") and evaluated against
+ * the `kind` footprint; the minimum over points goes to dd_min[r*T + h]
+ * (+inf when no point is valid).  dargmin (may be NULL) receives the index,
+ * in the caller's point array, of the lowest-index point attaining it (-1
+ * when none).                                                              */
+MPPI_API int sdf_min_poses(mppi_ctx ctx, const float* dposes, int K, int T, float dt, int state_offset,
+                  int kind, float* dd_min, int* dargmin);
+
+/* Sampling and rollout only (Algorithm 1 step 1): K perturbed control
+ * sequences around the nominal dU (device, T*nu row-major) and their Euler
+ * rollouts from q0 (host, 3 floats).  Outputs (device, any may be NULL):
+ * dposes K*T*4, deps K*T*nu (clipped perturbation), du K*T*nu (sampled
+ * control).  The noise of (rollout r, step h) is the deterministic function
+ * of (seed, step, r, h) described with mppi_step.                          */
+MPPI_API int mppi_rollout(mppi_ctx ctx, const mppi_params* prm, const float* q0, const float* dU,
+                 uint64_t seed, uint64_t step, float* dposes, float* deps, float* du);
+
+/* One control cycle, Algorithm 1:
+ *   1. eps_h^(r) = sigma * z with z standard normal from Philox4x64-10
+ *      (counter (h, r, step, 0), key (seed, 0)) and Box-Muller; the sampled
+ *      control is clipped to [u_min, u_max]; K Euler rollouts from q0.
+ *   2. d_min over the points (set_points) against the footprint of
+ *      prm->footprint_kind in every rollout body frame; costs J, unsafe flag
+ *      chi and augmented cost J~ (Section "Safety Penalties and Trajectory
+ *      Validation").
+ *   3. beta = min J~, omega = softmax(-(J~ - beta)/lambda), U += sum omega eps.
+ *   4. (prm->validate) re-roll the updated U, d_nom over the points; if every
+ *      d_nom >= d_safe: u* = U_0 and U is shifted left (last entry
+ *      repeated); otherwise u* = 0 and U = 0.
+ * q0: host, 3 floats (x, y, theta).  dU: device T*nu, updated in place.
+ * u_out: host, nu floats receiving u*.  valid_out (host, may be NULL)
+ * receives 1 if the nominal passed validation.  diag may be NULL.
+ * Synchronous: returns after u_out has been written.                       */
+MPPI_API int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, uint64_t seed,
+              uint64_t step, float* u_out, int* valid_out, const mppi_diag* diag);
+
+/* Kernel timing of the fused transform + signed distance + min stage of
+ * mppi_step (the dominant kernel), measured with HIP events recorded on the
+ * context's stream right before and after that launch.  enable != 0 turns
+ * recording on and resets the totals; enable == 0 turns it off.           */
+MPPI_API int mppi_set_profiling(mppi_ctx ctx, int enable);
+
+/* Totals since profiling was enabled: *ms = summed event time of the
+ * signed-distance launches of the sampled rollouts, *launches = their count.
+ * Synchronous.                                                             */
+MPPI_API int mppi_get_profile(mppi_ctx ctx, double* ms, long long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXACT_MPPI_H */

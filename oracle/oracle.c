@@ -541,3 +541,15 @@ EXPORT void orc_f32_normals_batch(uint64_t seed, uint64_t step, uint32_t h, uint
                                   long n, float* z) {
     for (long r = 0; r < n; ++r) orc_f32_normals(seed, step, (uint32_t)r, h, stream, z + 4 * r);
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Number of threads the OpenMP loops above use. */
+EXPORT int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

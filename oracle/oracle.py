@@ -83,8 +83,13 @@ def lib():
         L.orc_rollout_f32.argtypes = [i, i, i, i, f, f, vp, vp, vp, vp, vp, u64, u64, u64, i,
                                       vp, vp, vp]
         L.orc_rollout_nominal_f32.argtypes = [i, i, i, f, f, vp, vp, i, vp]
+        L.orc_num_threads.restype = i
         _lib = L
     return _lib
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def _p(a):

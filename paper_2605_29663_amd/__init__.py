@@ -1,0 +1,261 @@
+"""MI355X (gfx950) library for one MPPI control step with exact footprint signed distance.
+
+Thin ctypes binding over the C ABI declared in ``include/exact_mppi.h``:
+argument checking and marshalling only, every step runs in the HIP kernels of
+``libexact_mppi.so``.  PyTorch supplies device memory and streams.
+
+Loading fails loudly (``RuntimeError``) when the library has not been built;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch  # noqa: F401  (load torch's HIP runtime before the library binds to it)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libexact_mppi.so")
+
+MPPI_OK, MPPI_E_ARG, MPPI_E_FOOTPRINT, MPPI_E_NO_FOOTPRINT = 0, -1, -2, -3
+MPPI_E_CAPACITY, MPPI_E_HIP, MPPI_E_STATE = -4, -5, -6
+POLYGON, RECTS = 0, 1
+MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
+
+EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
+           "set_footprint", "set_points",
+           "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
+           "mppi_set_profiling", "mppi_get_profile")
+
+
+class MppiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class MppiParams(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("T", ctypes.c_int32), ("nu", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("footprint_kind", ctypes.c_int32),
+                ("dt", ctypes.c_float), ("lambda_", ctypes.c_float), ("wheelbase", ctypes.c_float),
+                ("sigma", ctypes.c_float * 3), ("u_min", ctypes.c_float * 3),
+                ("u_max", ctypes.c_float * 3), ("d_safe", ctypes.c_float),
+                ("w_coll", ctypes.c_float), ("w_rep", ctypes.c_float), ("w_inf", ctypes.c_float),
+                ("w_goal", ctypes.c_float), ("w_ctrl", ctypes.c_float * 3),
+                ("goal", ctypes.c_float * 2), ("state_offset", ctypes.c_int32),
+                ("validate", ctypes.c_int32)]
+
+
+class MppiDiag(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("d_min", "argmin", "J", "w", "poses", "eps", "u", "U_upd", "d_nom")]
+
+
+_lib = None
+
+
+def load():
+    """Load libexact_mppi.so (raises RuntimeError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2605_29663_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, f, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_uint64
+    L.mppi_create.argtypes = [ctypes.POINTER(vp), i, vp]
+    L.mppi_destroy.argtypes = [vp]
+    L.mppi_last_error.argtypes = [vp]
+    L.mppi_last_error.restype = ctypes.c_char_p
+    L.mppi_check_footprint.argtypes = [i, vp, i, ctypes.c_char_p, i]
+    L.set_footprint.argtypes = [vp, i, vp, i]
+    L.set_points.argtypes = [vp, vp, vp, vp, vp, vp, i]
+    L.sdf_polygon.argtypes = [vp, vp, vp, i, vp]
+    L.sdf_rectcover.argtypes = [vp, vp, vp, i, vp]
+    L.sdf_min_poses.argtypes = [vp, vp, i, i, f, i, i, vp, vp]
+    L.mppi_rollout.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp, vp, vp]
+    L.mppi_step.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp,
+                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(MppiDiag)]
+    L.mppi_set_profiling.argtypes = [vp, i]
+    L.mppi_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_longlong)]
+    for name in EXPORTS:
+        if name not in ("mppi_last_error",):
+            getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def check_footprint(kind, data):
+    """Host-only footprint validation: returns (code, message)."""
+    a = np.ascontiguousarray(np.asarray(data, dtype=np.float32))
+    count = a.shape[0] if a.ndim == 2 else a.size // (2 if kind == POLYGON else 4)
+    msg = ctypes.create_string_buffer(512)
+    rc = load().mppi_check_footprint(int(kind), a.ctypes.data_as(ctypes.c_void_p), int(count),
+                                     msg, 512)
+    return rc, msg.value.decode()
+
+
+def make_params(p) -> MppiParams:
+    """C parameter struct from a plain dict (the same dict the oracle takes)."""
+    m = MppiParams()
+    m.K, m.T, m.nu = int(p["K"]), int(p["T"]), int(p["nu"])
+    m.model = MODELS[p["model"]] if isinstance(p["model"], str) else int(p["model"])
+    m.footprint_kind = int(p["footprint_kind"])
+    m.dt, m.lambda_, m.wheelbase = float(p["dt"]), float(p["lambda_"]), float(p["wheelbase"])
+    for name in ("sigma", "u_min", "u_max", "w_ctrl"):
+        v = list(p[name])
+        arr = getattr(m, name)
+        for c in range(3):
+            arr[c] = float(v[c]) if c < len(v) else 0.0
+    for name in ("d_safe", "w_coll", "w_rep", "w_inf", "w_goal"):
+        setattr(m, name, float(p[name]))
+    m.goal[0], m.goal[1] = float(p["goal"][0]), float(p["goal"][1])
+    m.state_offset = int(p["state_offset"])
+    m.validate = int(p.get("validate", 1))
+    return m
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, device, name):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t), dtype=torch.float32)
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name}: float32 expected, got {t.dtype}")
+    return t.to(device).contiguous()
+
+
+class Context:
+    """One library context (device buffers for footprint, points and workspaces)."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.mppi_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.mppi_last_error(None).decode())
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mppi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.mppi_last_error(self.h).decode())
+
+    # ------------------------------------------------------------------ API
+    def set_footprint(self, kind, data):
+        a = np.ascontiguousarray(np.asarray(data, dtype=np.float32))
+        count = a.shape[0] if a.ndim == 2 else a.size // (2 if kind == POLYGON else 4)
+        self._check(self.lib.set_footprint(self.h, int(kind), a.ctypes.data_as(ctypes.c_void_p),
+                                           int(count)))
+
+    def set_points(self, x, y, vx=None, vy=None, valid=None):
+        x = _dev_f32(x, self.device, "x")
+        y = _dev_f32(y, self.device, "y")
+        vx = None if vx is None else _dev_f32(vx, self.device, "vx")
+        vy = None if vy is None else _dev_f32(vy, self.device, "vy")
+        if valid is not None:
+            valid = torch.as_tensor(np.asarray(valid) if not isinstance(valid, torch.Tensor)
+                                    else valid).to(self.device, torch.uint8).contiguous()
+        n = x.numel()
+        for t in (y, vx, vy, valid):
+            if t is not None and t.numel() != n:
+                raise ValueError("point arrays differ in length")
+        self._check(self.lib.set_points(self.h, _ptr(x), _ptr(y), _ptr(vx), _ptr(vy),
+                                        _ptr(valid), n))
+        # the copy is stream-ordered: keep the sources alive until the stream passes it
+        self._keep = [x, y, vx, vy, valid]
+
+    def _sdf(self, fn, px, py):
+        px = _dev_f32(px, self.device, "px")
+        py = _dev_f32(py, self.device, "py")
+        out = torch.empty_like(px)
+        self._check(fn(self.h, _ptr(px), _ptr(py), px.numel(), _ptr(out)))
+        return out
+
+    def sdf_polygon(self, px, py):
+        return self._sdf(self.lib.sdf_polygon, px, py)
+
+    def sdf_rectcover(self, px, py):
+        return self._sdf(self.lib.sdf_rectcover, px, py)
+
+    def sdf_min_poses(self, poses, dt=0.0, state_offset=1, kind=POLYGON, argmin=False):
+        """poses: (K, T, 4) (x, y, cos, sin).  Returns d_min (K, T) [and argmin]."""
+        poses = _dev_f32(poses, self.device, "poses")
+        K, T = poses.shape[0], poses.shape[1]
+        d = torch.empty((K, T), dtype=torch.float32, device=self.device)
+        am = torch.empty((K, T), dtype=torch.int32, device=self.device) if argmin else None
+        self._check(self.lib.sdf_min_poses(self.h, _ptr(poses), K, T, float(dt),
+                                           int(state_offset), int(kind), _ptr(d), _ptr(am)))
+        return (d, am) if argmin else d
+
+    def mppi_rollout(self, prm, q0, U, seed, step):
+        p = make_params(prm)
+        U = _dev_f32(U, self.device, "U")
+        K, T, nu = p.K, p.T, p.nu
+        poses = torch.empty((K, T, 4), dtype=torch.float32, device=self.device)
+        eps = torch.empty((K, T, nu), dtype=torch.float32, device=self.device)
+        us = torch.empty((K, T, nu), dtype=torch.float32, device=self.device)
+        q = (ctypes.c_float * 3)(*[float(v) for v in q0])
+        self._check(self.lib.mppi_rollout(self.h, ctypes.byref(p), q, _ptr(U), int(seed),
+                                          int(step), _ptr(poses), _ptr(eps), _ptr(us)))
+        return poses, eps, us
+
+    def mppi_set_profiling(self, enable=True):
+        self._check(self.lib.mppi_set_profiling(self.h, int(bool(enable))))
+
+    def mppi_get_profile(self):
+        """(total ms, launch count) of the timed signed-distance launches."""
+        ms, n = ctypes.c_double(), ctypes.c_longlong()
+        self._check(self.lib.mppi_get_profile(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def mppi_step(self, prm, q0, U, seed, step, diag=False, params=None):
+        """One control cycle.  U (T, nu) device float32 is updated in place.
+
+        Returns (u_star ndarray, valid bool, diag dict or None).
+        """
+        p = params if params is not None else make_params(prm)
+        if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.float32
+                and U.is_contiguous()):
+            raise TypeError("U must be a contiguous float32 CUDA tensor (updated in place)")
+        K, T, nu = p.K, p.T, p.nu
+        D = None
+        out = None
+        if diag:
+            dev = self.device
+            out = dict(d_min=torch.empty((K, T), device=dev),
+                       argmin=torch.empty((K, T), dtype=torch.int32, device=dev),
+                       J=torch.empty(K, device=dev), w=torch.empty(K, device=dev),
+                       poses=torch.empty((K, T, 4), device=dev),
+                       eps=torch.empty((K, T, nu), device=dev),
+                       u=torch.empty((K, T, nu), device=dev),
+                       U_upd=torch.empty((T, nu), device=dev),
+                       d_nom=torch.full((T,), math.nan, device=dev))
+            D = MppiDiag(*[out[k].data_ptr() for k in
+                           ("d_min", "argmin", "J", "w", "poses", "eps", "u", "U_upd", "d_nom")])
+        q = (ctypes.c_float * 3)(*[float(v) for v in q0])
+        u_out = (ctypes.c_float * 3)()
+        valid = ctypes.c_int(0)
+        self._check(self.lib.mppi_step(self.h, ctypes.byref(p), q, _ptr(U), int(seed), int(step),
+                                       u_out, ctypes.byref(valid),
+                                       ctypes.byref(D) if D is not None else None))
+        return np.array(u_out[:nu], dtype=np.float32), bool(valid.value), out

@@ -1,0 +1,610 @@
+// C ABI of the library (declared in include/exact_mppi.h): context, footprint
+// and obstacle-set management, and the orchestration of one control cycle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/exact_mppi.h"
+#include "kernels.hpp"
+
+using namespace emppi;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// A growable device buffer owned by the context.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            cap = 0;
+        }
+        const size_t want = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+}  // namespace
+
+struct mppi_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // footprint: polygon (padded vertices + point-wise tables) and rectangle cover
+    bool has_poly = false, has_rect = false;
+    int B = 0, BP = 0, R = 0, RP = 0;
+    DevBuf poly_verts, poly_tab_a, poly_tab_b, rects;
+    // obstacle points (compacted)
+    int n_points = 0;
+    bool moving = false;
+    DevBuf px, py, pvx, pvy, pidx, n_valid;
+    // step workspaces
+    DevBuf eps_ws, u_ws, poses_ws, jbase, jt, part, part_idx, unew, nom_poses, part_nom, out4;
+    float* h_out = nullptr;  // pinned
+    // profiling of the dominant launch
+    bool prof = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double prof_ms = 0.0;
+    long long prof_n = 0;
+};
+
+namespace {
+
+int fail(mppi_ctx ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                    \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            return fail((ctx), MPPI_E_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));    \
+    } while (0)
+
+// RAII guard that makes ctx->device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Proper intersection or touching of segments ab and cd (double precision).
+double orient2(const double* a, const double* b, const double* c) {
+    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+}
+bool on_segment(const double* a, const double* b, const double* p) {
+    return std::min(a[0], b[0]) <= p[0] && p[0] <= std::max(a[0], b[0]) &&
+           std::min(a[1], b[1]) <= p[1] && p[1] <= std::max(a[1], b[1]);
+}
+bool segments_meet(const double* a, const double* b, const double* c, const double* d) {
+    const double o1 = orient2(a, b, c), o2 = orient2(a, b, d);
+    const double o3 = orient2(c, d, a), o4 = orient2(c, d, b);
+    if (((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0)))
+        return true;
+    if (o1 == 0 && on_segment(a, b, c)) return true;
+    if (o2 == 0 && on_segment(a, b, d)) return true;
+    if (o3 == 0 && on_segment(c, d, a)) return true;
+    if (o4 == 0 && on_segment(c, d, b)) return true;
+    return false;
+}
+
+// Simple-polygon check: finite, no zero-length edge, non-zero area, and no
+// two non-adjacent edges meeting (adjacent edges may only share their common
+// vertex: a fold-back onto the previous edge is rejected too).
+int check_polygon(mppi_ctx ctx, const std::vector<double>& v, int B) {
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(ctx, MPPI_E_FOOTPRINT, "non-finite vertex coordinate");
+    double area2 = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double* p = &v[2 * b];
+        const double* q = &v[2 * ((b + 1) % B)];
+        if (p[0] == q[0] && p[1] == q[1])
+            return fail(ctx, MPPI_E_FOOTPRINT, "zero-length edge %d", b);
+        area2 += p[0] * q[1] - q[0] * p[1];
+    }
+    if (std::fabs(area2) * 0.5 < 1e-12) return fail(ctx, MPPI_E_FOOTPRINT, "polygon area below 1e-12");
+    for (int i = 0; i < B; ++i) {
+        const double* a = &v[2 * i];
+        const double* b = &v[2 * ((i + 1) % B)];
+        for (int j = i + 1; j < B; ++j) {
+            const double* c = &v[2 * j];
+            const double* d = &v[2 * ((j + 1) % B)];
+            const bool next = (j == i + 1), prev = ((j + 1) % B == i);
+            if (next || prev) {
+                // adjacent: collinear overlap beyond the shared vertex is a fold-back
+                const double* far = next ? d : c;          // the non-shared end of edge j
+                const double* far_i = next ? a : b;        // the non-shared end of edge i
+                const double* shared = next ? b : a;
+                if (orient2(a, b, far) == 0 && on_segment(a, b, far) &&
+                    !(far[0] == shared[0] && far[1] == shared[1]))
+                    return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d fold back", i, j);
+                if (orient2(c, d, far_i) == 0 && on_segment(c, d, far_i))
+                    return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d fold back", i, j);
+                continue;
+            }
+            if (segments_meet(a, b, c, d))
+                return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d touch or cross (not simple)", i, j);
+        }
+    }
+    return MPPI_OK;
+}
+
+bool valid_model(int model, int nu) {
+    switch (model) {
+    case MPPI_UNICYCLE:
+    case MPPI_ACKERMANN: return nu == 2;
+    case MPPI_OMNI: return nu == 3;
+    case MPPI_SPIN:
+    case MPPI_PARALLEL: return nu == 1;
+    default: return false;
+    }
+}
+
+int check_params(mppi_ctx ctx, const mppi_params* p) {
+    if (!p) return fail(ctx, MPPI_E_ARG, "params is NULL");
+    if (p->K < 1 || p->K > MPPI_MAX_K) return fail(ctx, MPPI_E_CAPACITY, "K=%d outside [1, %d]", p->K, MPPI_MAX_K);
+    if (p->T < 1 || p->T > MPPI_MAX_T) return fail(ctx, MPPI_E_CAPACITY, "T=%d outside [1, %d]", p->T, MPPI_MAX_T);
+    if (p->nu < 1 || p->nu > 3) return fail(ctx, MPPI_E_CAPACITY, "nu=%d outside [1, 3]", p->nu);
+    if (!valid_model(p->model, p->nu)) return fail(ctx, MPPI_E_ARG, "model %d does not take nu=%d", p->model, p->nu);
+    if (p->footprint_kind != MPPI_FP_POLYGON && p->footprint_kind != MPPI_FP_RECTS)
+        return fail(ctx, MPPI_E_ARG, "footprint_kind %d", p->footprint_kind);
+    if (!(p->dt > 0) || !(p->lambda > 0) || !std::isfinite(p->dt) || !std::isfinite(p->lambda))
+        return fail(ctx, MPPI_E_ARG, "dt and lambda must be positive and finite");
+    if (p->model == MPPI_ACKERMANN && !(p->wheelbase > 0))
+        return fail(ctx, MPPI_E_ARG, "wheelbase must be positive");
+    for (int c = 0; c < p->nu; ++c)
+        if (!(p->u_min[c] <= p->u_max[c]) || !(p->sigma[c] >= 0))
+            return fail(ctx, MPPI_E_ARG, "channel %d: need sigma >= 0 and u_min <= u_max", c);
+    if (p->footprint_kind == MPPI_FP_POLYGON && !ctx->has_poly)
+        return fail(ctx, MPPI_E_NO_FOOTPRINT, "no polygon footprint set");
+    if (p->footprint_kind == MPPI_FP_RECTS && !ctx->has_rect)
+        return fail(ctx, MPPI_E_NO_FOOTPRINT, "no rectangle cover set");
+    return MPPI_OK;
+}
+
+StepArgs make_args(const mppi_params* p, const float* q0, uint64_t seed, uint64_t step) {
+    StepArgs a{};
+    a.K = p->K;
+    a.Kpad = (p->K + WAVE - 1) / WAVE * WAVE;
+    a.T = p->T;
+    a.nu = p->nu;
+    a.model = p->model;
+    a.state_offset = p->state_offset ? 1 : 0;
+    a.dt = p->dt;
+    a.lambda = p->lambda;
+    a.wheelbase = p->wheelbase;
+    for (int c = 0; c < 3; ++c) {
+        const bool on = c < p->nu;
+        a.sigma[c] = on ? p->sigma[c] : 0.f;
+        a.umin[c] = on ? p->u_min[c] : 0.f;
+        a.umax[c] = on ? p->u_max[c] : 0.f;
+        a.w_ctrl[c] = on ? p->w_ctrl[c] : 0.f;
+        a.q0[c] = q0[c];
+    }
+    a.d_safe = p->d_safe;
+    a.w_coll = p->w_coll;
+    a.w_rep = p->w_rep;
+    a.w_inf = p->w_inf;
+    a.w_goal = p->w_goal;
+    a.goal[0] = p->goal[0];
+    a.goal[1] = p->goal[1];
+    a.seed = seed;
+    a.step = step;
+    a.stream = 0;
+    return a;
+}
+
+PointArgs point_args(mppi_ctx ctx) {
+    PointArgs pa;
+    pa.x = ctx->px.as<float>();
+    pa.y = ctx->py.as<float>();
+    pa.vx = ctx->moving ? ctx->pvx.as<float>() : nullptr;
+    pa.vy = ctx->moving ? ctx->pvy.as<float>() : nullptr;
+    pa.idx = ctx->pidx.as<int>();
+    pa.n_valid = ctx->n_valid.as<int>();
+    return pa;
+}
+
+// Chunking of the points over blockIdx.y: enough workgroups to fill the
+// chip several times over, chunks of at least 64 points.
+void choose_chunks(int npose, int n_points, int block, int& nchunk, int& chunk) {
+    const int pose_blocks = std::max(1, (npose + block - 1) / block);
+    const int target = 4096;
+    int nc = std::max(1, (target + pose_blocks - 1) / pose_blocks);
+    nc = std::min(nc, std::max(1, n_points / 64));
+    chunk = std::max(1, (n_points + nc - 1) / nc);
+    nc = std::max(1, (n_points + chunk - 1) / chunk);
+    nchunk = nc;
+}
+
+int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind, bool argmin,
+             DevBuf& part, DevBuf* part_idx, int& nchunk_out) {
+    const int block = npose >= 4096 ? 256 : 64;
+    int nchunk, chunk;
+    choose_chunks(npose, ctx->n_points, block, nchunk, chunk);
+    HIP_TRY(ctx, part.ensure(sizeof(float) * static_cast<size_t>(npose) * nchunk));
+    if (argmin) HIP_TRY(ctx, part_idx->ensure(sizeof(int) * static_cast<size_t>(npose) * nchunk));
+    DminLaunch L{};
+    L.poses = poses;
+    L.npose = npose;
+    L.pt = pt;
+    L.pts = point_args(ctx);
+    L.chunk = chunk;
+    L.nchunk = nchunk;
+    L.block = block;
+    L.kind = kind;
+    L.verts = ctx->poly_verts.as<float2>();
+    L.rects = ctx->rects.as<float4>();
+    L.padded = kind == 0 ? ctx->BP : ctx->RP;
+    L.argmin = argmin;
+    L.part = part.as<float>();
+    L.part_idx = argmin ? part_idx->as<int>() : nullptr;
+    HIP_TRY(ctx, launch_dmin(L, ctx->stream));
+    nchunk_out = nchunk;
+    return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mppi_create(mppi_ctx* out, int device, void* hip_stream) {
+    if (!out) return fail(nullptr, MPPI_E_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(nullptr, MPPI_E_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(nullptr, MPPI_E_ARG, "device %d of %d", device, n);
+    mppi_ctx ctx = new mppi_ctx_s;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    DeviceGuard g(device);
+    e = ctx->n_valid.ensure(sizeof(int));
+    if (e == hipSuccess) e = ctx->out4.ensure(4 * sizeof(float));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_out), 4 * sizeof(float), 0);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->n_valid.p, 0, sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        mppi_destroy(ctx);
+        return fail(nullptr, MPPI_E_HIP, "context setup: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return MPPI_OK;
+}
+
+int mppi_destroy(mppi_ctx ctx) {
+    if (!ctx) return MPPI_OK;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        DevBuf* bufs[] = {&ctx->poly_verts, &ctx->poly_tab_a, &ctx->poly_tab_b, &ctx->rects,
+                          &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
+                          &ctx->eps_ws, &ctx->u_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
+                          &ctx->part, &ctx->part_idx, &ctx->unew, &ctx->nom_poses,
+                          &ctx->part_nom, &ctx->out4};
+        for (DevBuf* b : bufs) b->release();
+        if (ctx->h_out) (void)hipHostFree(ctx->h_out);
+        if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+        if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    }
+    delete ctx;
+    return MPPI_OK;
+}
+
+const char* mppi_last_error(mppi_ctx ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int mppi_check_footprint(int kind, const float* host, int count, char* msg, int msg_len) {
+    mppi_ctx_s tmp;
+    int rc = MPPI_OK;
+    if (!host) {
+        rc = fail(&tmp, MPPI_E_ARG, "footprint data is NULL");
+    } else if (kind == MPPI_FP_POLYGON) {
+        if (count < 3 || count > MPPI_MAX_B) {
+            rc = fail(&tmp, MPPI_E_CAPACITY, "polygon needs 3..%d vertices, got %d", MPPI_MAX_B, count);
+        } else {
+            std::vector<double> v(2 * count);
+            for (int k = 0; k < 2 * count; ++k) v[k] = host[k];
+            rc = check_polygon(&tmp, v, count);
+        }
+    } else if (kind == MPPI_FP_RECTS) {
+        if (count < 1 || count > MPPI_MAX_R) {
+            rc = fail(&tmp, MPPI_E_CAPACITY, "rectangle cover needs 1..%d boxes, got %d", MPPI_MAX_R, count);
+        } else {
+            for (int j = 0; j < count && rc == MPPI_OK; ++j) {
+                for (int k = 0; k < 4; ++k)
+                    if (!std::isfinite(host[4 * j + k])) {
+                        rc = fail(&tmp, MPPI_E_FOOTPRINT, "box %d not finite", j);
+                        break;
+                    }
+                if (rc == MPPI_OK && (!(host[4 * j + 2] > 0) || !(host[4 * j + 3] > 0)))
+                    rc = fail(&tmp, MPPI_E_FOOTPRINT, "box %d: half extents must be positive", j);
+            }
+        }
+    } else {
+        rc = fail(&tmp, MPPI_E_ARG, "unknown footprint kind %d", kind);
+    }
+    if (msg && msg_len > 0) {
+        std::strncpy(msg, tmp.err.c_str(), static_cast<size_t>(msg_len) - 1);
+        msg[msg_len - 1] = 0;
+    }
+    return rc;
+}
+
+int set_footprint(mppi_ctx ctx, int kind, const float* host, int count) {
+    if (!ctx) return MPPI_E_ARG;
+    {
+        char msg[512];
+        const int rc = mppi_check_footprint(kind, host, count, msg, sizeof msg);
+        if (rc != MPPI_OK) return fail(ctx, rc, "%s", msg);
+    }
+    DeviceGuard g(ctx->device);
+    if (kind == MPPI_FP_POLYGON) {
+        const int BP = dmin_padded_count(0, count);
+        // padded vertex list for the fused kernel: repeats of vertex 0
+        std::vector<float> pv(2 * BP);
+        for (int b = 0; b < BP; ++b) {
+            const int s = b < count ? b : 0;
+            pv[2 * b] = host[2 * s];
+            pv[2 * b + 1] = host[2 * s + 1];
+        }
+        // point-wise tables: (x, y, ex, ey) and (ex/|e|^2, ey/|e|^2, ex/ey, 0)
+        std::vector<float> ta(4 * count), tb(4 * count);
+        for (int b = 0; b < count; ++b) {
+            const int n = (b + 1) % count;
+            const float x = host[2 * b], y = host[2 * b + 1];
+            const float ex = host[2 * n] - x, ey = host[2 * n + 1] - y;
+            const float l2 = std::fma(ex, ex, ey * ey);
+            const float inv = 1.0f / l2;
+            ta[4 * b] = x;
+            ta[4 * b + 1] = y;
+            ta[4 * b + 2] = ex;
+            ta[4 * b + 3] = ey;
+            tb[4 * b] = ex * inv;
+            tb[4 * b + 1] = ey * inv;
+            tb[4 * b + 2] = ey != 0.0f ? ex / ey : 0.0f;
+            tb[4 * b + 3] = 0.0f;
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, ctx->poly_verts.ensure(pv.size() * sizeof(float)));
+        HIP_TRY(ctx, ctx->poly_tab_a.ensure(ta.size() * sizeof(float)));
+        HIP_TRY(ctx, ctx->poly_tab_b.ensure(tb.size() * sizeof(float)));
+        HIP_TRY(ctx, hipMemcpy(ctx->poly_verts.p, pv.data(), pv.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(ctx, hipMemcpy(ctx->poly_tab_a.p, ta.data(), ta.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(ctx, hipMemcpy(ctx->poly_tab_b.p, tb.data(), tb.size() * sizeof(float), hipMemcpyHostToDevice));
+        ctx->B = count;
+        ctx->BP = BP;
+        ctx->has_poly = true;
+        return MPPI_OK;
+    }
+    if (kind == MPPI_FP_RECTS) {
+        const int RP = dmin_padded_count(1, count);
+        std::vector<float> rv(4 * RP);
+        for (int j = 0; j < RP; ++j)
+            for (int k = 0; k < 4; ++k) rv[4 * j + k] = host[4 * (j < count ? j : 0) + k];
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, ctx->rects.ensure(rv.size() * sizeof(float)));
+        HIP_TRY(ctx, hipMemcpy(ctx->rects.p, rv.data(), rv.size() * sizeof(float), hipMemcpyHostToDevice));
+        ctx->R = count;
+        ctx->RP = RP;
+        ctx->has_rect = true;
+        return MPPI_OK;
+    }
+    return fail(ctx, MPPI_E_ARG, "unknown footprint kind %d", kind);
+}
+
+int set_points(mppi_ctx ctx, const float* dx, const float* dy, const float* dvx, const float* dvy,
+               const unsigned char* dvalid, int n) {
+    if (!ctx) return MPPI_E_ARG;
+    if (n < 0) return fail(ctx, MPPI_E_ARG, "n < 0");
+    if (n > 0 && (!dx || !dy)) return fail(ctx, MPPI_E_ARG, "point arrays are NULL");
+    DeviceGuard g(ctx->device);
+    const bool moving = dvx || dvy;
+    const size_t cap = static_cast<size_t>(std::max(n, 1));
+    HIP_TRY(ctx, ctx->px.ensure(cap * sizeof(float)));
+    HIP_TRY(ctx, ctx->py.ensure(cap * sizeof(float)));
+    HIP_TRY(ctx, ctx->pidx.ensure(cap * sizeof(int)));
+    if (moving) {
+        HIP_TRY(ctx, ctx->pvx.ensure(cap * sizeof(float)));
+        HIP_TRY(ctx, ctx->pvy.ensure(cap * sizeof(float)));
+        // a missing velocity component is zero
+        if (!dvx) HIP_TRY(ctx, hipMemsetAsync(ctx->pvx.p, 0, cap * sizeof(float), ctx->stream));
+        if (!dvy) HIP_TRY(ctx, hipMemsetAsync(ctx->pvy.p, 0, cap * sizeof(float), ctx->stream));
+    }
+    HIP_TRY(ctx, launch_compact_points(dx, dy, dvx, dvy, dvalid, n, ctx->px.as<float>(),
+                                       ctx->py.as<float>(), dvx ? ctx->pvx.as<float>() : nullptr,
+                                       dvy ? ctx->pvy.as<float>() : nullptr, ctx->pidx.as<int>(),
+                                       ctx->n_valid.as<int>(), ctx->stream));
+    ctx->n_points = n;
+    ctx->moving = moving;
+    return MPPI_OK;
+}
+
+int sdf_polygon(mppi_ctx ctx, const float* dpx, const float* dpy, int n, float* dd) {
+    if (!ctx) return MPPI_E_ARG;
+    if (n < 0 || (n > 0 && (!dpx || !dpy || !dd))) return fail(ctx, MPPI_E_ARG, "bad arrays");
+    if (!ctx->has_poly) return fail(ctx, MPPI_E_NO_FOOTPRINT, "no polygon footprint set");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(ctx, launch_sdf_points(0, dpx, dpy, n, ctx->poly_tab_a.as<float4>(),
+                                   ctx->poly_tab_b.as<float4>(), ctx->B, dd, ctx->stream));
+    return MPPI_OK;
+}
+
+int sdf_rectcover(mppi_ctx ctx, const float* dpx, const float* dpy, int n, float* dd) {
+    if (!ctx) return MPPI_E_ARG;
+    if (n < 0 || (n > 0 && (!dpx || !dpy || !dd))) return fail(ctx, MPPI_E_ARG, "bad arrays");
+    if (!ctx->has_rect) return fail(ctx, MPPI_E_NO_FOOTPRINT, "no rectangle cover set");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(ctx, launch_sdf_points(1, dpx, dpy, n, ctx->rects.as<float4>(), nullptr, ctx->R, dd,
+                                   ctx->stream));
+    return MPPI_OK;
+}
+
+int sdf_min_poses(mppi_ctx ctx, const float* dposes, int K, int T, float dt, int state_offset,
+                  int kind, float* dd_min, int* dargmin) {
+    if (!ctx) return MPPI_E_ARG;
+    if (K < 0 || T < 1 || !dd_min || (K > 0 && !dposes)) return fail(ctx, MPPI_E_ARG, "bad arguments");
+    if (kind == MPPI_FP_POLYGON && !ctx->has_poly) return fail(ctx, MPPI_E_NO_FOOTPRINT, "no polygon footprint set");
+    if (kind == MPPI_FP_RECTS && !ctx->has_rect) return fail(ctx, MPPI_E_NO_FOOTPRINT, "no rectangle cover set");
+    if (kind != MPPI_FP_POLYGON && kind != MPPI_FP_RECTS) return fail(ctx, MPPI_E_ARG, "kind %d", kind);
+    const long long np = static_cast<long long>(K) * T;
+    if (np > (1ll << 30)) return fail(ctx, MPPI_E_CAPACITY, "K*T too large");
+    if (np == 0) return MPPI_OK;
+    DeviceGuard g(ctx->device);
+    PoseTime pt{1, T, state_offset ? 1 : 0, dt};
+    int nchunk = 1;
+    if (int rc = run_dmin(ctx, reinterpret_cast<const float4*>(dposes), static_cast<int>(np), pt,
+                          kind, dargmin != nullptr, ctx->part, &ctx->part_idx, nchunk))
+        return rc;
+    HIP_TRY(ctx, launch_dmin_finalize(ctx->part.as<float>(), dargmin ? ctx->part_idx.as<int>() : nullptr,
+                                      nchunk, static_cast<int>(np), dd_min, dargmin, ctx->stream));
+    return MPPI_OK;
+}
+
+static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
+                           float* deps, float* du) {
+    const size_t Kpad = A.Kpad, T = A.T, nu = A.nu;
+    HIP_TRY(ctx, ctx->eps_ws.ensure(sizeof(float) * T * nu * Kpad));
+    HIP_TRY(ctx, ctx->u_ws.ensure(sizeof(float) * T * nu * Kpad));
+    HIP_TRY(ctx, ctx->poses_ws.ensure(sizeof(float4) * T * Kpad));
+    HIP_TRY(ctx, ctx->jbase.ensure(sizeof(float) * Kpad));
+    RolloutOut o;
+    o.eps_ws = ctx->eps_ws.as<float>();
+    o.poses = ctx->poses_ws.as<float4>();
+    o.jbase = ctx->jbase.as<float>();
+    o.diag_poses = dposes;
+    o.diag_eps = deps;
+    o.diag_u = du;
+    HIP_TRY(ctx, launch_rollout(A, dU, ctx->u_ws.as<float>(), o, ctx->stream));
+    return MPPI_OK;
+}
+
+int mppi_rollout(mppi_ctx ctx, const mppi_params* prm, const float* q0, const float* dU,
+                 uint64_t seed, uint64_t step, float* dposes, float* deps, float* du) {
+    if (!ctx) return MPPI_E_ARG;
+    if (!prm || !q0 || !dU) return fail(ctx, MPPI_E_ARG, "NULL argument");
+    if (prm->K < 1 || prm->K > MPPI_MAX_K || prm->T < 1 || prm->T > MPPI_MAX_T)
+        return fail(ctx, MPPI_E_CAPACITY, "K or T out of range");
+    if (!valid_model(prm->model, prm->nu)) return fail(ctx, MPPI_E_ARG, "model/nu mismatch");
+    DeviceGuard g(ctx->device);
+    const StepArgs A = make_args(prm, q0, seed, step);
+    return rollout_into_ws(ctx, A, dU, dposes, deps, du);
+}
+
+int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, uint64_t seed,
+              uint64_t step, float* u_out, int* valid_out, const mppi_diag* diag) {
+    if (!ctx) return MPPI_E_ARG;
+    if (!q0 || !dU || !u_out) return fail(ctx, MPPI_E_ARG, "NULL argument");
+    if (int rc = check_params(ctx, prm)) return rc;
+    DeviceGuard g(ctx->device);
+    const StepArgs A = make_args(prm, q0, seed, step);
+    const mppi_diag D = diag ? *diag : mppi_diag{};
+    const int kind = prm->footprint_kind;
+    const size_t Kpad = A.Kpad, T = A.T, nu = A.nu;
+
+    // 1. sampling + rollouts
+    if (int rc = rollout_into_ws(ctx, A, dU, D.poses, D.eps, D.u)) return rc;
+    // 2. signed distances, min over points
+    int nchunk = 1;
+    PoseTime pt{A.Kpad, A.T, A.state_offset, A.dt};
+    if (ctx->prof) HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    if (int rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), static_cast<int>(T * Kpad), pt, kind,
+                          D.argmin != nullptr, ctx->part, &ctx->part_idx, nchunk))
+        return rc;
+    if (ctx->prof) HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIP_TRY(ctx, ctx->jt.ensure(sizeof(float) * Kpad));
+    HIP_TRY(ctx, launch_cost(A, ctx->part.as<float>(), D.argmin ? ctx->part_idx.as<int>() : nullptr,
+                             nchunk, ctx->jbase.as<float>(), nullptr, ctx->jt.as<float>(), D.d_min,
+                             D.argmin, ctx->stream));
+    if (D.J)
+        HIP_TRY(ctx, hipMemcpyAsync(D.J, ctx->jt.p, sizeof(float) * A.K, hipMemcpyDeviceToDevice, ctx->stream));
+    // 3. weights and update
+    HIP_TRY(ctx, ctx->unew.ensure(sizeof(float) * T * nu));
+    HIP_TRY(ctx, launch_update(A, ctx->jt.as<float>(), ctx->eps_ws.as<float>(), dU,
+                               ctx->unew.as<float>(), D.w, ctx->stream));
+    // 4. validation
+    int nchunk_nom = 1;
+    if (prm->validate) {
+        HIP_TRY(ctx, ctx->nom_poses.ensure(sizeof(float4) * T));
+        HIP_TRY(ctx, launch_nominal(A, ctx->unew.as<float>(), ctx->nom_poses.as<float4>(), ctx->stream));
+        PoseTime ptn{1, A.T, A.state_offset, A.dt};
+        if (int rc = run_dmin(ctx, ctx->nom_poses.as<float4>(), A.T, ptn, kind, false,
+                              ctx->part_nom, nullptr, nchunk_nom))
+            return rc;
+    }
+    HIP_TRY(ctx, launch_finalize(A, prm->validate ? 1 : 0, ctx->part_nom.as<float>(), nchunk_nom,
+                                 ctx->unew.as<float>(), dU, ctx->out4.as<float>(), D.U_upd,
+                                 D.d_nom, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_out, ctx->out4.p, 4 * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->prof) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->prof_ms += ms;
+        ctx->prof_n += 1;
+    }
+    for (int c = 0; c < prm->nu; ++c) u_out[c] = ctx->h_out[c];
+    if (valid_out) *valid_out = ctx->h_out[3] != 0.0f;
+    return MPPI_OK;
+}
+
+int mppi_set_profiling(mppi_ctx ctx, int enable) {
+    if (!ctx) return MPPI_E_ARG;
+    DeviceGuard g(ctx->device);
+    if (enable && !ctx->ev0) {
+        HIP_TRY(ctx, hipEventCreate(&ctx->ev0));
+        HIP_TRY(ctx, hipEventCreate(&ctx->ev1));
+    }
+    ctx->prof = enable != 0;
+    ctx->prof_ms = 0.0;
+    ctx->prof_n = 0;
+    return MPPI_OK;
+}
+
+int mppi_get_profile(mppi_ctx ctx, double* ms, long long* launches) {
+    if (!ctx || !ms || !launches) return MPPI_E_ARG;
+    *ms = ctx->prof_ms;
+    *launches = ctx->prof_n;
+    return MPPI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal interface between the C ABI layer and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emppi {
+
+constexpr int WAVE = 64;
+constexpr int DMIN_TILE = 1024;  // points staged in LDS per tile
+
+// Step parameters as the kernels see them (POD, passed by value).
+struct StepArgs {
+    int K, Kpad, T, nu, model, state_offset;
+    float dt, lambda, wheelbase;
+    float sigma[3], umin[3], umax[3];
+    float d_safe, w_coll, w_rep, w_inf, w_goal, w_ctrl[3], goal[2];
+    float q0[3];
+    uint64_t seed, step, stream;
+};
+
+// Valid obstacle points, compacted in index order (the count lives on the
+// device so that a mask change needs no host round trip).
+struct PointArgs {
+    const float* x;
+    const float* y;
+    const float* vx;  // nullptr for static point sets
+    const float* vy;
+    const int* idx;   // caller's index of each compacted point
+    const int* n_valid;
+};
+
+// Time of pose g for moving points: h = (g / div) % mod, t = (h + off) dt.
+struct PoseTime {
+    int div, mod, off;
+    float dt;
+};
+
+// One launch of the fused transform + signed distance + min-over-points
+// stage: npose poses, points split into nchunk chunks of `chunk` points;
+// partial minima of the signed squared distance go to part[c * npose + g].
+struct DminLaunch {
+    const float4* poses;
+    int npose;
+    PoseTime pt;
+    PointArgs pts;
+    int chunk, nchunk, block;
+    int kind;          // 0 polygon, 1 rectangle cover
+    const float2* verts;  // polygon, padded to `padded` vertices (repeats of v0)
+    const float4* rects;  // rectangle cover, padded to `padded` boxes (repeats of box 0)
+    int padded;
+    bool argmin;
+    float* part;
+    int* part_idx;
+};
+
+hipError_t launch_dmin(const DminLaunch& L, hipStream_t s);
+int dmin_padded_count(int kind, int count);  // bucket a footprint size is padded to
+
+hipError_t launch_dmin_finalize(const float* part, const int* part_idx, int nchunk, int npose,
+                                float* d_out, int* idx_out, hipStream_t s);
+
+hipError_t launch_sdf_points(int kind, const float* px, const float* py, int n,
+                             const float4* tab_a, const float4* tab_b, int count, float* out,
+                             hipStream_t s);
+
+hipError_t launch_compact_points(const float* x, const float* y, const float* vx, const float* vy,
+                                 const unsigned char* valid, int n, float* ox, float* oy,
+                                 float* ovx, float* ovy, int* oidx, int* n_valid, hipStream_t s);
+
+struct RolloutOut {
+    float* eps_ws;   // [T][nu][Kpad]
+    float4* poses;   // [T][Kpad]
+    float* jbase;    // [Kpad]
+    float* diag_poses;  // [K][T][4] or nullptr
+    float* diag_eps;    // [K][T][nu]
+    float* diag_u;      // [K][T][nu]
+};
+
+hipError_t launch_rollout(const StepArgs& P, const float* U, float* u_ws, const RolloutOut& o,
+                          hipStream_t s);
+
+hipError_t launch_cost(const StepArgs& P, const float* part, const int* part_idx, int nchunk,
+                       const float* jbase, const int* pidx_unused, float* jt, float* diag_dmin,
+                       int* diag_argmin, hipStream_t s);
+
+hipError_t launch_update(const StepArgs& P, const float* jt, const float* eps_ws, const float* U,
+                         float* Unew, float* diag_w, hipStream_t s);
+
+hipError_t launch_nominal(const StepArgs& P, const float* Unew, float4* nom_poses, hipStream_t s);
+
+hipError_t launch_finalize(const StepArgs& P, int validate, const float* part_nom, int nchunk,
+                           const float* Unew, float* U, float* out4, float* diag_unew,
+                           float* diag_dnom, hipStream_t s);
+
+}  // namespace emppi

@@ -1,0 +1,383 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (the contract of the method): signed distances within 1e-5 m
+absolute; signs identical except where the oracle's |d| < 1e-6 m; sampled
+noise and rollouts bit-identical; augmented costs within 1e-5 relative (FP32
+sum of at most 128 terms); weights and updated controls within 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_29663_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL_D = 1e-5
+SIGN_BAND = 1e-6
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_29663_amd as p
+    p.load()
+    return p
+
+
+@pytest.fixture(scope="module")
+def ctx(pkg):
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def assert_sdf_close(d_gpu, d_orc, tol=TOL_D, band=SIGN_BAND):
+    d_gpu = np.asarray(d_gpu, dtype=np.float64)
+    fin = np.isfinite(d_orc)
+    assert np.array_equal(np.isfinite(d_gpu), fin)
+    assert np.all(d_gpu[~fin] == d_orc[~fin])
+    err = np.abs(d_gpu[fin] - d_orc[fin])
+    assert err.max(initial=0.0) <= tol, f"max |d err| {err.max()}"
+    far = fin & (np.abs(d_orc) >= band)
+    assert np.array_equal(np.signbit(d_gpu[far]), np.signbit(d_orc[far]))
+
+
+# ------------------------------------------------------------- point-wise SDF
+
+def _near_boundary_points(V, rng, n):
+    E = np.roll(V, -1, axis=0) - V
+    b = rng.integers(0, len(V), n)
+    t = rng.uniform(0, 1, n)
+    nrm = np.stack([E[b, 1], -E[b, 0]], 1) / np.linalg.norm(E[b], axis=1)[:, None]
+    off = rng.choice([-1, 1], n) * 10 ** rng.uniform(-7, -1, n)
+    return V[b] + t[:, None] * E[b] + off[:, None] * nrm
+
+
+POLYS = {"L8": scenes.FOOTPRINT_L8, "towed16": scenes.FOOTPRINT_TOWED16,
+         "union20": scenes.RECTS_4_BOUNDARY, "gapL": scenes.FOOTPRINT_GAP_L,
+         "tri": np.array([(0.0, 0.0), (1.0, 0.1), (0.3, 0.9)]),
+         "star32": scenes.star_polygon(np.random.default_rng(32), 32),
+         "star5": scenes.star_polygon(np.random.default_rng(5), 5)}
+
+
+@pytest.mark.parametrize("name", sorted(POLYS))
+def test_sdf_polygon_pointwise(ctx, pkg, orc, name):
+    V = POLYS[name]
+    rng = np.random.default_rng(sum(map(ord, name)))
+    far = rng.uniform(-25, 25, size=(100000, 2))      # the paper's 50 x 50 m query box
+    near = rng.uniform(-2, 2, size=(50000, 2))
+    edge = _near_boundary_points(V, rng, 30000)
+    P = np.concatenate([far, near, edge, V]).astype(np.float32)
+    ctx.set_footprint(pkg.POLYGON, V)
+    d = _np(ctx.sdf_polygon(P[:, 0].copy(), P[:, 1].copy()))
+    assert_sdf_close(d, orc.sdf_polygon(V, P[:, 0], P[:, 1]))
+
+
+RECTS = {"rects4": scenes.RECTS_4, "gapL": scenes.RECTS_GAP_L, "one": np.array([(0.3, -0.2, 0.5, 0.25)]),
+         "L": scenes.SHAPES_LTF["L"][1], "F": scenes.SHAPES_LTF["F"][1],
+         "r32": np.concatenate([np.random.default_rng(1).uniform(-1, 1, (32, 2)),
+                                np.random.default_rng(2).uniform(0.05, 0.5, (32, 2))], 1)}
+
+
+@pytest.mark.parametrize("name", sorted(RECTS))
+def test_sdf_rectcover_pointwise(ctx, pkg, orc, name):
+    R = RECTS[name]
+    rng = np.random.default_rng(len(name))
+    P = np.concatenate([rng.uniform(-25, 25, (100000, 2)), rng.uniform(-1.5, 1.5, (80000, 2))])
+    P = P.astype(np.float32)
+    ctx.set_footprint(pkg.RECTS, R)
+    d = _np(ctx.sdf_rectcover(P[:, 0].copy(), P[:, 1].copy()))
+    assert_sdf_close(d, orc.sdf_rectcover(R, P[:, 0], P[:, 1]))
+
+
+def test_sdf_pointwise_empty_and_ragged(ctx, pkg, orc):
+    ctx.set_footprint(pkg.POLYGON, scenes.FOOTPRINT_L8)
+    assert ctx.sdf_polygon(np.zeros(0, np.float32), np.zeros(0, np.float32)).numel() == 0
+    for n in (1, 63, 257):
+        P = np.random.default_rng(n).uniform(-2, 2, (n, 2)).astype(np.float32)
+        d = _np(ctx.sdf_polygon(P[:, 0].copy(), P[:, 1].copy()))
+        assert_sdf_close(d, orc.sdf_polygon(scenes.FOOTPRINT_L8, P[:, 0], P[:, 1]))
+
+
+# ------------------------------------------------------------- fused d_min
+
+def _random_poses(rng, K, T, spread=2.0):
+    th = rng.uniform(-math.pi, math.pi, (K, T))
+    P = np.stack([rng.uniform(-spread, spread, (K, T)), rng.uniform(-spread, spread, (K, T)),
+                  np.cos(th), np.sin(th)], -1)
+    return P.astype(np.float32)
+
+
+@pytest.mark.parametrize("kind,moving,masked", [(0, False, False), (0, True, True),
+                                                (1, False, True), (1, True, False)])
+def test_sdf_min_poses(ctx, pkg, orc, kind, moving, masked):
+    rng = np.random.default_rng(10 * kind + 2 * moving + masked)
+    K, T, N, dt = 100, 7, 2500, 0.1            # 700 poses (ragged vs 64), 3 LDS tiles
+    poses = _random_poses(rng, K, T)
+    ox, oy = rng.uniform(-4, 4, N).astype(np.float32), rng.uniform(-4, 4, N).astype(np.float32)
+    vx = vy = None
+    if moving:
+        vx, vy = rng.uniform(-1, 1, N).astype(np.float32), rng.uniform(-1, 1, N).astype(np.float32)
+    valid = (rng.uniform(size=N) < 0.6).astype(np.uint8) if masked else None
+    geom = scenes.FOOTPRINT_TOWED16 if kind == 0 else scenes.RECTS_4
+    ctx.set_footprint(kind, geom)
+    ctx.set_points(ox, oy, vx, vy, valid)
+    d, am = ctx.sdf_min_poses(poses, dt=dt, state_offset=1, kind=kind, argmin=True)
+    d, am = _np(d), _np(am)
+    tau = ((np.arange(T) + 1) * np.float64(np.float32(dt)))[None].repeat(K, 0).ravel()
+    d_o, am_o = orc.dmin(poses.reshape(-1, 4), tau, ox, oy, vx, vy, valid, kind, geom,
+                         want_argmin=True)
+    assert_sdf_close(d.ravel(), d_o)
+    # the oracle's distance at the GPU's argmin point equals the oracle minimum
+    am = am.ravel()
+    assert np.all((am >= 0) == (am_o >= 0))
+    if valid is not None:
+        assert np.all(valid[am[am >= 0]] == 1)
+    sel = np.flatnonzero(am >= 0)
+    for k in sel[:: max(1, len(sel) // 300)]:
+        i = am[k]
+        d_at = orc.dmin(poses.reshape(-1, 4)[k:k + 1], tau[k:k + 1], ox[i:i + 1], oy[i:i + 1],
+                        None if vx is None else vx[i:i + 1], None if vy is None else vy[i:i + 1],
+                        None, kind, geom)[0]
+        assert abs(d_at - d_o[k]) <= TOL_D
+
+
+def test_sdf_min_poses_empty_and_all_masked(ctx, pkg):
+    ctx.set_footprint(pkg.POLYGON, scenes.FOOTPRINT_L8)
+    poses = _random_poses(np.random.default_rng(0), 3, 5)
+    ctx.set_points(np.zeros(0, np.float32), np.zeros(0, np.float32))
+    d, am = ctx.sdf_min_poses(poses, argmin=True)
+    assert np.all(np.isposinf(_np(d))) and np.all(_np(am) == -1)
+    x = np.float32([0.1, 0.2, np.nan, 5.0])
+    ctx.set_points(x, x, valid=np.uint8([0, 0, 1, 0]))      # the only "valid" one is NaN
+    d, am = ctx.sdf_min_poses(poses, argmin=True)
+    assert np.all(np.isposinf(_np(d))) and np.all(_np(am) == -1)
+
+
+def test_sdf_min_poses_large_n_ragged(ctx, pkg, orc):
+    """Many chunks and LDS tiles: N = 30001 points, 130 poses, polygon B = 32."""
+    rng = np.random.default_rng(7)
+    V = POLYS["star32"]
+    poses = _random_poses(rng, 13, 10, spread=5.0)
+    N = 30001
+    ox, oy = rng.uniform(-8, 8, N).astype(np.float32), rng.uniform(-8, 8, N).astype(np.float32)
+    ctx.set_footprint(pkg.POLYGON, V)
+    ctx.set_points(ox, oy)
+    d = _np(ctx.sdf_min_poses(poses, dt=0.05, kind=pkg.POLYGON)).ravel()
+    assert_sdf_close(d, orc.dmin(poses.reshape(-1, 4), None, ox, oy, kind=0, geom=V))
+
+
+# ------------------------------------------------------------- rollouts
+
+MODEL_CASES = [("c1", {}), ("c2", {}), ("c3", {}),
+               ("c1", dict(model="spin", nu=1, sigma=(0.7,), u_min=(-1.0,), u_max=(1.0,))),
+               ("c1", dict(model="parallel", nu=1, sigma=(0.5,), u_min=(-0.6,), u_max=(0.6,))),
+               ("c2", dict(state_offset=0))]
+
+
+@pytest.mark.parametrize("cfg,over", MODEL_CASES)
+def test_rollout_bit_exact(ctx, pkg, orc, cfg, over):
+    prm = scenes.params(cfg, K=300, T=33, **over)
+    rng = np.random.default_rng(3)
+    lo, hi = np.float32(prm["u_min"]), np.float32(prm["u_max"])
+    U = (rng.uniform(size=(prm["T"], prm["nu"])) * (hi - lo) * 0.8 + lo * 0.8).astype(np.float32)
+    q0 = np.float32([0.3, -1.2, 2.9])
+    poses, eps, us = ctx.mppi_rollout(prm, q0, U, seed=0xC0FFEE, step=17)
+    p_o, e_o, u_o = orc.rollout_f32(prm, q0, U, 0xC0FFEE, 17)
+    np.testing.assert_array_equal(_np(eps), e_o)
+    np.testing.assert_array_equal(_np(us), u_o)
+    np.testing.assert_array_equal(_np(poses), p_o)
+
+
+# ------------------------------------------------------------- full step
+
+def _step_case(name, K=None, N=None, T=None):
+    prm, sc = scenes.config(name)
+    if K:
+        prm["K"] = K
+    if T:
+        prm["T"] = T
+    if N:
+        keep = slice(0, N)
+        sc = {k: (v[keep] if isinstance(v, np.ndarray) and v.ndim == 1 and v.size > 1000 else v)
+              for k, v in sc.items()}
+    return prm, sc
+
+
+def _load_scene(ctx, pkg, prm, sc):
+    if prm["footprint_kind"] == 0:
+        ctx.set_footprint(pkg.POLYGON, sc["polygon"])
+    else:
+        ctx.set_footprint(pkg.RECTS, sc["rects"])
+    ctx.set_points(sc["ox"], sc["oy"], sc.get("ovx"), sc.get("ovy"), sc.get("valid"))
+
+
+def _check_step_rows(orc, prm, sc, q0, U0, seed, step, u_star, valid, D, U_after, sample=None):
+    """Row-by-row parity of one step from the GPU's own intermediates."""
+    K, T, nu = prm["K"], prm["T"], prm["nu"]
+    kind, geom = (0, sc["polygon"]) if prm["footprint_kind"] == 0 else (1, sc["rects"])
+    # a1, a2: noise and rollouts bit-exact
+    p_o, e_o, u_o = orc.rollout_f32(prm, q0, U0, seed, step)
+    poses, eps, us = _np(D["poses"]), _np(D["eps"]), _np(D["u"])
+    np.testing.assert_array_equal(eps, e_o)
+    np.testing.assert_array_equal(us, u_o)
+    np.testing.assert_array_equal(poses, p_o)
+    # a3-a6: d_min on the GPU's poses (all, or a sample at full size)
+    d = _np(D["d_min"]).astype(np.float64)
+    tau = orc.tau_of(prm, T, K)
+    flat = np.arange(K * T) if sample is None else sample
+    d_o = orc.dmin(poses.reshape(-1, 4)[flat], tau.ravel()[flat], sc["ox"], sc["oy"],
+                   sc.get("ovx"), sc.get("ovy"), sc.get("valid"), kind, geom)
+    assert_sdf_close(d.ravel()[flat], d_o)
+    # a7: J~ from the GPU's d_min, poses and controls
+    J, chi, Jt = orc.costs(prm, poses[..., :2], us, d)
+    Jg = _np(D["J"]).astype(np.float64)
+    np.testing.assert_allclose(Jg, Jt, rtol=1e-5)
+    # a8, a9: weights and update from the GPU's J~
+    w_o = orc.weights(Jg, prm["lambda_"])
+    np.testing.assert_allclose(_np(D["w"]), w_o, atol=1e-6, rtol=1e-5)
+    U_upd_o = orc.update(U0, w_o, eps)
+    U_upd = _np(D["U_upd"])
+    np.testing.assert_allclose(U_upd, U_upd_o, atol=1e-5)
+    # a10: nominal re-rollout of the GPU's update, validation, shift / reset
+    if prm.get("validate", 1):
+        nom = orc.rollout_nominal_f32(prm, q0, U_upd)
+        dn_o = orc.dmin(nom, orc.tau_of(prm, T), sc["ox"], sc["oy"], sc.get("ovx"),
+                        sc.get("ovy"), sc.get("valid"), kind, geom)
+        dn = _np(D["d_nom"]).astype(np.float64)
+        assert_sdf_close(dn, dn_o)
+        near = np.abs(dn_o - np.float32(prm["d_safe"])) < TOL_D
+        # the decision on the GPU's own d_nom is reproduced exactly, and the
+        # oracle's d_nom gives the same decision unless a value sits at d_safe
+        ok_o, us_o, Un_o = orc.validate_shift(U_upd, dn, prm["d_safe"])
+        assert valid == ok_o
+        if not near.any():
+            assert valid == orc.validate_shift(U_upd, dn_o, prm["d_safe"])[0]
+        np.testing.assert_array_equal(u_star, np.float32(us_o))
+        np.testing.assert_array_equal(_np(U_after), np.float32(Un_o))
+    return Jt
+
+
+@pytest.mark.parametrize("name,K,N,T", [("c1", None, None, None), ("c2", 192, 1500, None),
+                                        ("c3", 128, 2100, 24)])
+def test_step_parity_small(ctx, pkg, orc, name, K, N, T):
+    import torch
+    prm, sc = _step_case(name, K, N, T)
+    _load_scene(ctx, pkg, prm, sc)
+    rng = np.random.default_rng(11)
+    U0 = (0.3 * rng.standard_normal((prm["T"], prm["nu"]))).astype(np.float32)
+    U0 = np.clip(U0, np.float32(prm["u_min"]), np.float32(prm["u_max"]))
+    q0 = np.float32([0.05, -0.02, 0.03])
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=0x5EED, step=3, diag=True)
+    _check_step_rows(orc, prm, sc, q0, U0, 0x5EED, 3, u_star, valid, D, Ut)
+
+
+def test_step_matches_oracle_from_scratch_c1(ctx, pkg, orc):
+    """End to end on the small unicycle case: the oracle runs the whole cycle
+    itself (double-precision SDF, costs, update, validation)."""
+    import torch
+    prm, sc = scenes.config("c1")
+    _load_scene(ctx, pkg, prm, sc)
+    U0 = np.zeros((prm["T"], 2), np.float32)
+    q0 = np.zeros(3, np.float32)
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=1, step=0, diag=True)
+    ref = orc.mppi_step(prm, q0, U0, sc, 1, 0)
+    assert_sdf_close(_np(D["d_min"]).ravel(), ref["d"].ravel())
+    # rollouts whose d_min sits within 1e-5 of 0 or d_safe may legitimately
+    # differ in their penalty branch; none do in this scene
+    dd = ref["d"]
+    edge = np.any((np.abs(dd) < TOL_D) | (np.abs(dd - prm["d_safe"]) < TOL_D), axis=1)
+    np.testing.assert_allclose(_np(D["J"])[~edge], ref["Jt"][~edge], rtol=1e-5)
+    np.testing.assert_allclose(_np(D["U_upd"]), ref["U_upd"], atol=1e-5)
+    assert valid == ref["valid"]
+    np.testing.assert_allclose(u_star, ref["u_star"], atol=1e-5)
+
+
+def test_step_edge_cases(ctx, pkg, orc):
+    import torch
+    # K = 1, T = 1, triangle footprint, no points: always valid, U += eps
+    prm = scenes.params("c1", K=1, T=1)
+    ctx.set_footprint(pkg.POLYGON, POLYS["tri"])
+    ctx.set_points(np.zeros(0, np.float32), np.zeros(0, np.float32))
+    U0 = np.float32([[0.2, 0.1]])
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, np.zeros(3, np.float32), Ut, 9, 9, diag=True)
+    assert valid and np.all(np.isposinf(_np(D["d_min"])))
+    assert _np(D["w"])[0] == 1.0
+    _, e_o, _ = orc.rollout_f32(prm, np.zeros(3, np.float32), U0, 9, 9)
+    np.testing.assert_allclose(u_star, U0[0] + e_o[0, 0], atol=1e-6)
+    # a wall of points on the path: validation fails -> hold and reset
+    prm = scenes.params("c1", K=64, T=10, sigma=(1e-3, 1e-3), validate=1)
+    ctx.set_footprint(pkg.POLYGON, scenes.FOOTPRINT_L8)
+    ys = np.linspace(-2, 2, 200).astype(np.float32)
+    ctx.set_points(np.full(200, 0.8, np.float32), ys)
+    Ut = torch.tensor(np.tile(np.float32([1.0, 0.0]), (10, 1)), device="cuda")
+    u_star, valid, _ = ctx.mppi_step(prm, np.zeros(3, np.float32), Ut, 1, 0)
+    assert not valid and np.all(u_star == 0) and torch.all(Ut == 0)
+    # validate = 0: always execute and shift
+    prm["validate"] = 0
+    Ut = torch.tensor(np.tile(np.float32([1.0, 0.0]), (10, 1)), device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, np.zeros(3, np.float32), Ut, 1, 0, diag=True)
+    assert valid
+    np.testing.assert_array_equal(u_star, _np(D["U_upd"])[0])
+
+
+def test_step_errors(ctx, pkg):
+    import torch
+    prm = scenes.params("c1")
+    Ut = torch.zeros((prm["T"], 2), device="cuda")
+    c2 = pkg.Context(0)
+    with pytest.raises(pkg.MppiError) as e:
+        c2.mppi_step(prm, np.zeros(3), Ut, 1, 0)
+    assert e.value.code == pkg.MPPI_E_NO_FOOTPRINT
+    c2.set_footprint(pkg.POLYGON, scenes.FOOTPRINT_L8)
+    for bad in (dict(K=0), dict(T=129), dict(nu=3), dict(lambda_=0.0)):
+        with pytest.raises(pkg.MppiError):
+            c2.mppi_step(dict(prm, **bad), np.zeros(3), Ut, 1, 0)
+    with pytest.raises(pkg.MppiError) as e:
+        c2.set_footprint(pkg.POLYGON, [(0, 0), (1, 1), (1, 0), (0, 1)])
+    assert e.value.code == pkg.MPPI_E_FOOTPRINT
+    c2.close()
+
+
+def test_step_deterministic(ctx, pkg):
+    import torch
+    prm, sc = _step_case("c3", K=256, N=3000, T=20)
+    _load_scene(ctx, pkg, prm, sc)
+    outs = []
+    for _ in range(3):
+        Ut = torch.zeros((prm["T"], prm["nu"]), device="cuda")
+        u, v, D = ctx.mppi_step(prm, np.zeros(3, np.float32), Ut, 5, 5, diag=True)
+        outs.append((u, v, {k: _np(t) for k, t in D.items()}, _np(Ut)))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and o[1] == outs[0][1]
+        for k in o[2]:
+            assert np.array_equal(o[2][k], outs[0][2][k], equal_nan=True), k
+        assert np.array_equal(o[3], outs[0][3])
+
+
+# ------------------------------------------------------------- full sizes
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_step_full_size_sampled(ctx, pkg, orc, name):
+    """Full-size configuration in the benchmark's launch shape; d_min checked on
+    a random sample of 256 (rollout, step) poses, everything else in full."""
+    import torch
+    prm, sc = scenes.config(name)
+    _load_scene(ctx, pkg, prm, sc)
+    U0 = np.zeros((prm["T"], prm["nu"]), np.float32)
+    q0 = np.zeros(3, np.float32)
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, q0, Ut, 0x5EED0002, 0, diag=True)
+    sample = np.random.default_rng(0).choice(prm["K"] * prm["T"], 256, replace=False)
+    _check_step_rows(orc, prm, sc, q0, U0, 0x5EED0002, 0, u_star, valid, D, Ut, sample=sample)
