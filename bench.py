@@ -27,8 +27,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one wave64 VALU instruction per CU per clock.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X FP32 VALU issue ceiling: the published FP32 vector peak (157.3 TFLOP/s)
+# counts 2 flops per FMA lane-instruction, i.e. 78.6e12 lane-instructions/s =
+# 256 CUs x 128 lanes/clock x 2.4 GHz.
+VALU_PEAK_TOPS = 157.3 / 2
 
 # Minimal VALU lane-instructions per unit of work (derivation in the design doc):
 #   polygon: 12 per (pose, point, edge) + 4 per (pose, point)
@@ -43,8 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rollouts", type=int, default=768,
-                    help="rollouts in the oracle's bounded sample of the step")
+    ap.add_argument("--cpu-reps", type=int, default=4,
+                    help="whole oracle steps timed for the CPU baseline")
     return ap.parse_args()
 
 
@@ -88,6 +90,7 @@ def main():
     q0 = (0.0, 0.0, 0.0)
     seed = 0x5EED0002
 
+    tuned = ctx.mppi_autotune(None, reps=3, params=params)
     for i in range(args.warmup):
         ctx.mppi_step(None, q0, U, seed, i, params=params)
     torch.cuda.synchronize()
@@ -138,22 +141,23 @@ def main():
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": traffic_record(kernel_src, workload),
-                     "kernel_ms": k_avg_ms, "launches": k_n},
+                     "kernel_ms": k_avg_ms, "launches": k_n,
+                     "tiles": {"block": tuned[0], "chunks": tuned[1]}},
     }
 
     if not args.no_cpu_baseline:
         sys.path.insert(0, ROOT)
         from oracle import oracle as orc
-        Ks = min(args.cpu_rollouts, K)
-        prm_s = dict(prm, K=Ks)
+        reps = max(1, args.cpu_reps)
         ts = time.perf_counter()
-        orc.mppi_step(prm_s, np.zeros(3, np.float32), np.zeros((T, nu), np.float32), sc, seed, 0)
+        for k in range(reps):
+            orc.mppi_step(prm, np.zeros(3, np.float32), np.zeros((T, nu), np.float32), sc, seed, k)
         cpu_s = time.perf_counter() - ts
-        cpu_pairs = (Ks * T + (T if prm["validate"] else 0)) * N * P
-        out["cpu_baseline"] = {"value": cpu_pairs / cpu_s, "unit": "evals/s",
+        out["cpu_baseline"] = {"value": reps * pairs_step / cpu_s, "unit": "evals/s",
+                               "ms_per_step": cpu_s * 1e3 / reps,
                                "cores": orc.num_threads(), "kind": "oracle",
-                               "sample": f"whole oracle step with {Ks} of {K} rollouts "
-                                         f"(full T={T}, N={N}, {P} primitives), {cpu_s:.1f} s"}
+                               "sample": f"{reps} whole oracle steps of the same workload "
+                                         f"(K={K}, T={T}, N={N}, {P} primitives), {cpu_s:.1f} s"}
     print(json.dumps(out))
     ctx.close()
 

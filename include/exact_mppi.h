@@ -205,6 +205,23 @@ MPPI_API int mppi_rollout(mppi_ctx ctx, const mppi_params* prm, const float* q0,
 MPPI_API int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, uint64_t seed,
               uint64_t step, float* u_out, int* valid_out, const mppi_diag* diag);
 
+/* Tile-shape autotuner for the fused transform + signed distance + min
+ * stage of mppi_step: for prm's shape and the footprint and points currently
+ * set, time every candidate (workgroup size in {64, 128, 256} poses, number of
+ * point chunks) on one sampled step with HIP events (reps launches each) and
+ * keep the fastest for this context; mppi_step then uses it whenever the
+ * shape (kind, padded primitive count, moving points, K*T, N) matches.
+ * out_block / out_nchunk (host, may be NULL) receive the choice.  Results do
+ * not depend on the choice (bit-identical).  Synchronous.                  */
+MPPI_API int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block,
+                           int* out_nchunk);
+
+/* Fix the tile shape of every fused signed-distance launch of this context
+ * (block = poses per workgroup: 64, 128 or 256; nchunk = point chunks, >= 1);
+ * block = 0 returns to the autotuned / default shapes.  Results are
+ * bit-identical for every shape; this exists for tests and experiments.   */
+MPPI_API int mppi_set_tiles(mppi_ctx ctx, int block, int nchunk);
+
 /* Kernel timing of the fused transform + signed distance + min stage of
  * mppi_step (the dominant kernel), measured with HIP events recorded on the
  * context's stream right before and after that launch.  enable != 0 turns

@@ -27,7 +27,7 @@ MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
            "set_footprint", "set_points",
            "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
-           "mppi_set_profiling", "mppi_get_profile")
+           "mppi_autotune", "mppi_set_tiles", "mppi_set_profiling", "mppi_get_profile")
 
 
 class MppiError(RuntimeError):
@@ -79,6 +79,9 @@ def load():
     L.mppi_rollout.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp, vp, vp]
     L.mppi_step.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(MppiDiag)]
+    L.mppi_autotune.argtypes = [vp, ctypes.POINTER(MppiParams), i, ctypes.POINTER(i),
+                                ctypes.POINTER(i)]
+    L.mppi_set_tiles.argtypes = [vp, i, i]
     L.mppi_set_profiling.argtypes = [vp, i]
     L.mppi_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_longlong)]
@@ -218,6 +221,17 @@ class Context:
         self._check(self.lib.mppi_rollout(self.h, ctypes.byref(p), q, _ptr(U), int(seed),
                                           int(step), _ptr(poses), _ptr(eps), _ptr(us)))
         return poses, eps, us
+
+    def mppi_autotune(self, prm, reps=3, params=None):
+        """Time the candidate tile shapes for prm's shape; returns (block, nchunk)."""
+        p = params if params is not None else make_params(prm)
+        b, c = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.mppi_autotune(self.h, ctypes.byref(p), int(reps), ctypes.byref(b),
+                                           ctypes.byref(c)))
+        return b.value, c.value
+
+    def mppi_set_tiles(self, block=0, nchunk=0):
+        self._check(self.lib.mppi_set_tiles(self.h, int(block), int(nchunk)))
 
     def mppi_set_profiling(self, enable=True):
         self._check(self.lib.mppi_set_profiling(self.h, int(bool(enable))))

@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/exact_mppi.h"
@@ -62,8 +64,11 @@ struct mppi_ctx_s {
     bool moving = false;
     DevBuf px, py, pvx, pvy, pidx, n_valid;
     // step workspaces
-    DevBuf eps_ws, u_ws, poses_ws, jbase, jt, part, part_idx, unew, nom_poses, part_nom, out4;
+    DevBuf eps_ws, poses_ws, jbase, jt, part, part_idx, unew, nom_poses, part_nom, out4;
     float* h_out = nullptr;  // pinned
+    // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
+    std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
+    int force_block = 0, force_nchunk = 0;  // mppi_set_tiles
     // profiling of the dominant launch
     bool prof = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -243,23 +248,57 @@ PointArgs point_args(mppi_ctx ctx) {
     return pa;
 }
 
-// Chunking of the points over blockIdx.y: enough workgroups to fill the
-// chip several times over, chunks of at least 64 points.
-void choose_chunks(int npose, int n_points, int block, int& nchunk, int& chunk) {
+// Waves per SIMD the fused kernel runs at (its register budget), used to
+// estimate how many workgroups are resident at once.
+int dmin_waves_per_simd(int kind, int padded) {
+    if (kind == 1) return 8;
+    return padded <= 8 ? 6 : padded <= 16 ? 4 : padded <= 20 ? 3 : 2;
+}
+
+// Default tile shape: chunks of at least 32 points, and a workgroup count
+// close to a whole number of "rounds" of resident workgroups so that the
+// last round is not a nearly empty tail (all workgroups do equal work).
+void choose_tiles(int kind, int padded, int npose, int n_points, int& block, int& nchunk, int& chunk) {
+    block = npose >= 4096 ? 256 : 64;
     const int pose_blocks = std::max(1, (npose + block - 1) / block);
-    const int target = 4096;
-    int nc = std::max(1, (target + pose_blocks - 1) / pose_blocks);
-    nc = std::min(nc, std::max(1, n_points / 64));
-    chunk = std::max(1, (n_points + nc - 1) / nc);
-    nc = std::max(1, (n_points + chunk - 1) / chunk);
-    nchunk = nc;
+    const int resident = 256 * 4 * dmin_waves_per_simd(kind, padded) / (block / WAVE);
+    const int max_chunks = std::max(1, n_points / 32);
+    int best_nc = 1;
+    double best_eff = -1.0;
+    for (int nc = 1; nc <= std::min(max_chunks, 4096); ++nc) {
+        const long long wgs = static_cast<long long>(pose_blocks) * nc;
+        const double rounds = static_cast<double>(wgs) / resident;
+        const double eff = rounds / std::ceil(rounds);      // fill of the last round
+        const double score = eff * std::min(1.0, rounds / 4.0);  // prefer >= 4 rounds
+        if (score > best_eff + 1e-9) {
+            best_eff = score;
+            best_nc = nc;
+        }
+        if (rounds > 16) break;
+    }
+    chunk = std::max(1, (n_points + best_nc - 1) / best_nc);
+    nchunk = std::max(1, (n_points + chunk - 1) / chunk);
 }
 
 int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind, bool argmin,
-             DevBuf& part, DevBuf* part_idx, int& nchunk_out) {
-    const int block = npose >= 4096 ? 256 : 64;
-    int nchunk, chunk;
-    choose_chunks(npose, ctx->n_points, block, nchunk, chunk);
+             DevBuf& part, DevBuf* part_idx, int& nchunk_out, int force_block = 0,
+             int force_nchunk = 0) {
+    const int padded = kind == 0 ? ctx->BP : ctx->RP;
+    int block, nchunk, chunk;
+    choose_tiles(kind, padded, npose, ctx->n_points, block, nchunk, chunk);
+    const auto it = ctx->tuned.find(std::make_tuple(kind, padded, ctx->moving ? 1 : 0, npose, ctx->n_points));
+    if (it != ctx->tuned.end()) {
+        block = it->second.first;
+        nchunk = it->second.second;
+    }
+    if (ctx->force_block) {
+        block = ctx->force_block;
+        nchunk = ctx->force_nchunk;
+    }
+    if (force_block) block = force_block;
+    if (force_nchunk) nchunk = force_nchunk;
+    chunk = std::max(1, (ctx->n_points + nchunk - 1) / nchunk);
+    nchunk = std::max(1, (ctx->n_points + chunk - 1) / chunk);
     HIP_TRY(ctx, part.ensure(sizeof(float) * static_cast<size_t>(npose) * nchunk));
     if (argmin) HIP_TRY(ctx, part_idx->ensure(sizeof(int) * static_cast<size_t>(npose) * nchunk));
     DminLaunch L{};
@@ -273,7 +312,7 @@ int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind
     L.kind = kind;
     L.verts = ctx->poly_verts.as<float2>();
     L.rects = ctx->rects.as<float4>();
-    L.padded = kind == 0 ? ctx->BP : ctx->RP;
+    L.padded = padded;
     L.argmin = argmin;
     L.part = part.as<float>();
     L.part_idx = argmin ? part_idx->as<int>() : nullptr;
@@ -283,6 +322,9 @@ int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind
 }
 
 }  // namespace
+
+static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
+                           float* deps, float* du);
 
 extern "C" {
 
@@ -317,7 +359,7 @@ int mppi_destroy(mppi_ctx ctx) {
         (void)hipStreamSynchronize(ctx->stream);
         DevBuf* bufs[] = {&ctx->poly_verts, &ctx->poly_tab_a, &ctx->poly_tab_b, &ctx->rects,
                           &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
-                          &ctx->eps_ws, &ctx->u_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
+                          &ctx->eps_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
                           &ctx->part, &ctx->part_idx, &ctx->unew, &ctx->nom_poses,
                           &ctx->part_nom, &ctx->out4};
         for (DevBuf* b : bufs) b->release();
@@ -504,7 +546,6 @@ static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, flo
                            float* deps, float* du) {
     const size_t Kpad = A.Kpad, T = A.T, nu = A.nu;
     HIP_TRY(ctx, ctx->eps_ws.ensure(sizeof(float) * T * nu * Kpad));
-    HIP_TRY(ctx, ctx->u_ws.ensure(sizeof(float) * T * nu * Kpad));
     HIP_TRY(ctx, ctx->poses_ws.ensure(sizeof(float4) * T * Kpad));
     HIP_TRY(ctx, ctx->jbase.ensure(sizeof(float) * Kpad));
     RolloutOut o;
@@ -514,7 +555,7 @@ static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, flo
     o.diag_poses = dposes;
     o.diag_eps = deps;
     o.diag_u = du;
-    HIP_TRY(ctx, launch_rollout(A, dU, ctx->u_ws.as<float>(), o, ctx->stream));
+    HIP_TRY(ctx, launch_rollout(A, dU, o, ctx->stream));
     return MPPI_OK;
 }
 
@@ -553,7 +594,7 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
     if (ctx->prof) HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIP_TRY(ctx, ctx->jt.ensure(sizeof(float) * Kpad));
     HIP_TRY(ctx, launch_cost(A, ctx->part.as<float>(), D.argmin ? ctx->part_idx.as<int>() : nullptr,
-                             nchunk, ctx->jbase.as<float>(), nullptr, ctx->jt.as<float>(), D.d_min,
+                             nchunk, ctx->jbase.as<float>(), ctx->jt.as<float>(), D.d_min,
                              D.argmin, ctx->stream));
     if (D.J)
         HIP_TRY(ctx, hipMemcpyAsync(D.J, ctx->jt.p, sizeof(float) * A.K, hipMemcpyDeviceToDevice, ctx->stream));
@@ -584,6 +625,75 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
     }
     for (int c = 0; c < prm->nu; ++c) u_out[c] = ctx->h_out[c];
     if (valid_out) *valid_out = ctx->h_out[3] != 0.0f;
+    return MPPI_OK;
+}
+
+int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block, int* out_nchunk) {
+    if (!ctx) return MPPI_E_ARG;
+    if (int rc = check_params(ctx, prm)) return rc;
+    if (reps < 1) reps = 3;
+    DeviceGuard g(ctx->device);
+    const float q0[3] = {0.f, 0.f, 0.f};
+    const StepArgs A = make_args(prm, q0, 0x7E57ull, 0);
+    // poses of one sampled step around a zero nominal
+    HIP_TRY(ctx, ctx->unew.ensure(sizeof(float) * A.T * A.nu));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->unew.p, 0, sizeof(float) * A.T * A.nu, ctx->stream));
+    if (int rc = rollout_into_ws(ctx, A, ctx->unew.as<float>(), nullptr, nullptr, nullptr)) return rc;
+    const int kind = prm->footprint_kind;
+    const int padded = kind == 0 ? ctx->BP : ctx->RP;
+    const int npose = A.T * A.Kpad;
+    PoseTime pt{A.Kpad, A.T, A.state_offset, A.dt};
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    int best_b = 0, best_c = 0;
+    float best_ms = 1e30f;
+    const int blocks[] = {64, 128, 256};
+    const int chunk_counts[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 13, 16, 20, 24, 32, 40, 48, 64, 96, 128};
+    int rc = MPPI_OK;
+    for (int b : blocks) {
+        for (int nc : chunk_counts) {
+            if (nc > 1 && ctx->n_points / nc < 32) continue;
+            int nchunk = 1;
+            // one untimed launch, then reps timed ones
+            rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), npose, pt, kind, false, ctx->part, nullptr, nchunk, b, nc);
+            if (rc) break;
+            hipError_t e = hipEventRecord(e0, ctx->stream);
+            for (int k = 0; k < reps && rc == MPPI_OK; ++k)
+                rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), npose, pt, kind, false, ctx->part, nullptr, nchunk, b, nc);
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(ctx, MPPI_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+                break;
+            }
+            ms /= reps;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_b = b;
+                best_c = nc;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    ctx->tuned[std::make_tuple(kind, padded, ctx->moving ? 1 : 0, npose, ctx->n_points)] = {best_b, best_c};
+    if (out_block) *out_block = best_b;
+    if (out_nchunk) *out_nchunk = best_c;
+    return MPPI_OK;
+}
+
+int mppi_set_tiles(mppi_ctx ctx, int block, int nchunk) {
+    if (!ctx) return MPPI_E_ARG;
+    if (block != 0 && block != 64 && block != 128 && block != 256)
+        return fail(ctx, MPPI_E_ARG, "block must be 0, 64, 128 or 256");
+    if (block != 0 && nchunk < 1) return fail(ctx, MPPI_E_ARG, "nchunk must be >= 1");
+    ctx->force_block = block;
+    ctx->force_nchunk = block ? nchunk : 0;
     return MPPI_OK;
 }
 

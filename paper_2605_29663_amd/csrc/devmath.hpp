@@ -5,9 +5,10 @@
 // behaviour is its own) but spelled out here from their textbook
 // definitions: Cody-Waite reduction by pi/2 with a three-float split, Taylor
 // polynomials on [-pi/4, pi/4], and log via 2 atanh((m-1)/(m+1)).  Every
-// +, -, *, / and sqrt is one IEEE binary32 operation (the library is built
-// with -ffp-contract=off and correctly rounded division and square root);
-// every fma is written out with __builtin_fmaf.
+// +, -, * and / is one IEEE binary32 operation (the library is built with
+// -ffp-contract=off and correctly rounded division); every fma is written
+// out with __builtin_fmaf; the square root is seq_sqrt below, because the
+// compiler lowers the f32 square root to the hardware's 1-ulp instruction.
 //
 // Philox4x64-10 follows Salmon, Moraes, Dror and Shaw, "Parallel random
 // numbers: as easy as 1, 2, 3" (SC'11): ten rounds of the 4x64 S-box with the
@@ -81,6 +82,25 @@ __device__ __forceinline__ float seq_log(float x) {
     return __builtin_fmaf(fe, LN2_HI, __builtin_fmaf(fe, LN2_LO, lnm));
 }
 
+// Correctly rounded square root.  v_sqrt_f32 is accurate to 1 ulp, so the
+// IEEE result is s or one of its float neighbours s-, s+.  With exact fused
+// residuals: x <= s * s-  means sqrt(x) is below the rounding boundary
+// between s- and s (the geometric mean of s- and s lies below their midpoint,
+// and no float x falls between s * s- and the squared midpoint), so the
+// result is s-; x > s * s+ likewise means s+.  Tiny inputs are scaled by 2^32
+// (result by 2^-16) so that the hardware instruction never sees a denormal.
+__device__ __forceinline__ float seq_sqrt(float x) {
+    const bool tiny = x < 0x1.0p-96f;
+    const float xs = tiny ? x * 0x1.0p+32f : x;
+    const float s = __builtin_amdgcn_sqrtf(xs);
+    const float sd = __uint_as_float(__float_as_uint(s) - 1u);
+    const float su = __uint_as_float(__float_as_uint(s) + 1u);
+    float r = s;
+    if (__builtin_fmaf(-sd, s, xs) <= 0.0f) r = sd;
+    if (__builtin_fmaf(-su, s, xs) > 0.0f) r = su;
+    return tiny ? r * 0x1.0p-16f : r;
+}
+
 __device__ __forceinline__ float seq_tan(float x) {
     float s, c;
     seq_sincos(x, s, c);
@@ -132,7 +152,7 @@ __device__ __forceinline__ void normals4(uint64_t seed, uint64_t step, uint32_t 
     for (int p = 0; p < 2; ++p) {
         const float u1 = word_uniform(w.v[2 * p]);
         const float u2 = word_uniform(w.v[2 * p + 1]);
-        const float rad = __fsqrt_rn(-2.0f * seq_log(u1));
+        const float rad = seq_sqrt(-2.0f * seq_log(u1));
         float s, c;
         seq_sincos(TWO_PI * u2, s, c);
         z[2 * p] = rad * c;

@@ -6,7 +6,8 @@
 namespace emppi {
 
 constexpr int WAVE = 64;
-constexpr int DMIN_TILE = 1024;  // points staged in LDS per tile
+constexpr int DMIN_TILE = 1024;      // points staged in LDS per tile
+constexpr int MPPI_MAX_T_DEV = 128;  // horizon capacity (MPPI_MAX_T of the C ABI)
 
 // Step parameters as the kernels see them (POD, passed by value).
 struct StepArgs {
@@ -76,12 +77,11 @@ struct RolloutOut {
     float* diag_u;      // [K][T][nu]
 };
 
-hipError_t launch_rollout(const StepArgs& P, const float* U, float* u_ws, const RolloutOut& o,
-                          hipStream_t s);
+hipError_t launch_rollout(const StepArgs& P, const float* U, const RolloutOut& o, hipStream_t s);
 
 hipError_t launch_cost(const StepArgs& P, const float* part, const int* part_idx, int nchunk,
-                       const float* jbase, const int* pidx_unused, float* jt, float* diag_dmin,
-                       int* diag_argmin, hipStream_t s);
+                       const float* jbase, float* jt, float* diag_dmin, int* diag_argmin,
+                       hipStream_t s);
 
 hipError_t launch_update(const StepArgs& P, const float* jt, const float* eps_ws, const float* U,
                          float* Unew, float* diag_w, hipStream_t s);

@@ -1,113 +1,22 @@
-// Fused rollout-frame transform + exact signed distance + min over points
-// (the hot stage of one MPPI step), the point-wise signed-distance kernels,
+// Single-scene kernels of the fused rollout-frame transform + exact signed
+// distance + min over points stage, the point-wise signed-distance kernels,
 // and the obstacle-point compaction that implements the validity mask.
-//
-// Paper: Section "Signed Distance Evaluation" (rollout-frame transform,
-// box distance, polygon distance with ray-casting sign) and Section "Batched
-// Rollout and Distance Computation" (K x T x N queries, masked min).
-//
-// Mapping on gfx950 (wave64, VALU-bound):
-//   one lane = one pose (rollout r, horizon h); the footprint is rotated into
-//   the lane's frame once per launch (7 registers per polygon edge); every
-//   obstacle point is broadcast to all lanes from LDS, so the inner loop is
-//   pure per-lane VALU work with no cross-lane traffic, and the min over
-//   points is a private running minimum in a register.  Points are split
-//   into chunks over blockIdx.y; the per-chunk minima are merged by the
-//   consumer (fixed order, hence deterministic).
-//   Distances are kept squared and signed, s = sign(d) d^2 (monotone in d),
-//   so one square root per pose replaces one per (point, edge).
-#include "kernels.hpp"
+// The per-lane work is in sdf_device.hpp (shared with the batched kernel).
+#include "sdf_device.hpp"
 
 namespace emppi {
 
 namespace {
 
-__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+// Grid: x over poses (one lane each), y over point chunks of `chunk` points.
+// Partial minima of the signed squared distance go to part[chunk_id][pose].
+// Waves per SIMD the register budget is tuned for (512 VGPRs per lane).
+template <int BP>
+constexpr int poly_waves() { return BP <= 8 ? 6 : BP <= 16 ? 4 : BP <= 20 ? 3 : 2; }
 
-// One polygon edge against point (dx, dy) in the frame where the edge is
-// (X, Y) -> (X + EX, Y + EY): squared point-to-segment distance with the
-// clipped projection alpha = clamp(w.e / |e|^2, 0, 1) (SX, SY = e / |e|^2),
-// and the ray-casting quantities: "vertex above the point" (wy < 0) and
-// "crossing right of the point" (wx < wy * EX / EY, SL = EX / EY).
-struct EdgeEval {
-    float d2;
-    bool above;
-    bool right;
-};
-
-__device__ __forceinline__ EdgeEval edge_eval(float dx, float dy, float X, float Y, float EX,
-                                              float EY, float SX, float SY, float SL) {
-    const float wx = dx - X, wy = dy - Y;
-    const float t = clamp01(__builtin_fmaf(wy, SY, wx * SX));
-    const float rx = __builtin_fmaf(-t, EX, wx);
-    const float ry = __builtin_fmaf(-t, EY, wy);
-    EdgeEval e;
-    e.d2 = __builtin_fmaf(ry, ry, rx * rx);
-    e.above = wy < 0.0f;
-    e.right = wx < wy * SL;
-    return e;
-}
-
-// Signed squared distance of one box (centre c, half extents h) to the
-// body-frame point (px, py): with a = |p - c| - h, i = max(a_x, a_y) and
-// j = max(min(a_x, a_y), 0), sign(d) d^2 = i |i| + j^2, which equals
-// |max(a,0)|^2 outside and -(max(a_x,a_y))^2 inside (the box formula).
-__device__ __forceinline__ float box_s(float px, float py, float4 b) {
-    const float ax = fabsf(px - b.x) - b.z;
-    const float ay = fabsf(py - b.y) - b.w;
-    const float i = fmaxf(ax, ay);
-    const float j = fmaxf(fminf(ax, ay), 0.0f);
-    return __builtin_fmaf(j, j, i * fabsf(i));
-}
-
-__device__ __forceinline__ float pose_tau(const PoseTime& pt, int g) {
-    const int h = (g / pt.div) % pt.mod;
-    return static_cast<float>(h + pt.off) * pt.dt;
-}
-
-__device__ __forceinline__ float signed_sqrt(float s) {
-    return s < 0.0f ? -__fsqrt_rn(-s) : __fsqrt_rn(s);
-}
-
-// Stage points [t0, t0 + tn) of the compacted set into LDS.
-template <bool MOVING>
-__device__ __forceinline__ void stage_points(float* lds, const PointArgs& pts, int t0, int tn) {
-    if (MOVING) {
-        float4* l4 = reinterpret_cast<float4*>(lds);
-        for (int i = threadIdx.x; i < tn; i += blockDim.x)
-            l4[i] = make_float4(pts.x[t0 + i], pts.y[t0 + i], pts.vx[t0 + i], pts.vy[t0 + i]);
-    } else {
-        float2* l2 = reinterpret_cast<float2*>(lds);
-        for (int i = threadIdx.x; i < tn; i += blockDim.x)
-            l2[i] = make_float2(pts.x[t0 + i], pts.y[t0 + i]);
-    }
-}
-
-// Point i of the staged tile at time tau, relative to the pose position.
-template <bool MOVING>
-__device__ __forceinline__ void point_rel(const float* lds, int i, float tau, float qx, float qy,
-                                          float& dx, float& dy) {
-    if (MOVING) {
-        const float4 o = reinterpret_cast<const float4*>(lds)[i];
-        dx = __builtin_fmaf(o.z, tau, o.x) - qx;
-        dy = __builtin_fmaf(o.w, tau, o.y) - qy;
-    } else {
-        const float2 o = reinterpret_cast<const float2*>(lds)[i];
-        dx = o.x - qx;
-        dy = o.y - qy;
-    }
-}
-
-// ---------------------------------------------------------------- polygon
-// BP = padded vertex count (multiple of 4; padding repeats vertex 0, giving
-// zero-length edges that never change the min and never straddle).
-// The footprint is used in a frame centred at the pose and aligned with the
-// planning frame: vertex b becomes R(theta) v_b, and each point enters as
-// o - t (its position relative to the pose).  The distance is rotation
-// invariant and the crossing parity does not depend on the ray direction, so
-// this equals the body-frame evaluation R(theta)^T (o - t) vs v_b.
 template <int BP, bool MOVING, bool ARGMIN>
-__global__ __launch_bounds__(256) void k_dmin_poly(const float4* __restrict__ poses, int npose,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(poly_waves<BP>())))
+void k_dmin_poly(const float4* __restrict__ poses, int npose,
                                                    PoseTime pt, PointArgs pts, int chunk,
                                                    const float2* __restrict__ verts,
                                                    float* __restrict__ part,
@@ -117,63 +26,12 @@ __global__ __launch_bounds__(256) void k_dmin_poly(const float4* __restrict__ po
     const bool live = g < npose;
     const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
     const float tau = MOVING ? pose_tau(pt, g) : 0.0f;
-
-    float X[BP], Y[BP], EX[BP], EY[BP], SX[BP], SY[BP], SL[BP];
-#pragma unroll
-    for (int b = 0; b < BP; ++b) {
-        const float2 v = verts[b];
-        X[b] = __builtin_fmaf(q.z, v.x, -(q.w * v.y));
-        Y[b] = __builtin_fmaf(q.w, v.x, q.z * v.y);
-    }
-#pragma unroll
-    for (int b = 0; b < BP; ++b) {
-        const int bn = (b + 1) % BP;
-        EX[b] = X[bn] - X[b];
-        EY[b] = Y[bn] - Y[b];
-        const float l2 = __builtin_fmaf(EX[b], EX[b], EY[b] * EY[b]);
-        const float inv = l2 > 0.0f ? 1.0f / l2 : 0.0f;
-        SX[b] = EX[b] * inv;
-        SY[b] = EY[b] * inv;
-        SL[b] = EY[b] != 0.0f ? EX[b] / EY[b] : 0.0f;
-    }
-
     const int nv = *pts.n_valid;
     const int c0 = blockIdx.y * chunk;
     const int c1 = min(c0 + chunk, nv);
-    float best = INFINITY;
-    int besti = -1;
-    for (int t0 = c0; t0 < c1; t0 += DMIN_TILE) {
-        const int tn = min(DMIN_TILE, c1 - t0);
-        __syncthreads();
-        stage_points<MOVING>(lds, pts, t0, tn);
-        __syncthreads();
-        for (int i = 0; i < tn; ++i) {
-            float dx, dy;
-            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
-            EdgeEval e = edge_eval(dx, dy, X[0], Y[0], EX[0], EY[0], SX[0], SY[0], SL[0]);
-            float m = e.d2;
-            const bool above0 = e.above;
-            bool above = e.above, right = e.right, odd = false;
-#pragma unroll
-            for (int b = 1; b < BP; ++b) {
-                e = edge_eval(dx, dy, X[b], Y[b], EX[b], EY[b], SX[b], SY[b], SL[b]);
-                m = fminf(m, e.d2);
-                odd ^= (above != e.above) & right;
-                above = e.above;
-                right = e.right;
-            }
-            odd ^= (above != above0) & right;
-            const float s = odd ? -m : m;
-            if (ARGMIN) {
-                if (s < best) {
-                    best = s;
-                    besti = t0 + i;
-                }
-            } else {
-                best = fminf(best, s);
-            }
-        }
-    }
+    float best;
+    int besti;
+    dmin_poly_range<BP, MOVING, ARGMIN>(q, tau, pts, c0, c1, verts, lds, best, besti);
     if (live) {
         const size_t o = static_cast<size_t>(blockIdx.y) * npose + g;
         part[o] = best;
@@ -181,9 +39,6 @@ __global__ __launch_bounds__(256) void k_dmin_poly(const float4* __restrict__ po
     }
 }
 
-// ---------------------------------------------------------------- rectangles
-// RP = padded box count (padding repeats box 0).  Points are rotated into
-// the body frame, p = R(theta)^T (o - t), then evaluated against each box.
 template <int RP, bool MOVING, bool ARGMIN>
 __global__ __launch_bounds__(256) void k_dmin_rect(const float4* __restrict__ poses, int npose,
                                                    PoseTime pt, PointArgs pts, int chunk,
@@ -195,38 +50,12 @@ __global__ __launch_bounds__(256) void k_dmin_rect(const float4* __restrict__ po
     const bool live = g < npose;
     const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
     const float tau = MOVING ? pose_tau(pt, g) : 0.0f;
-    float4 bx[RP];
-#pragma unroll
-    for (int j = 0; j < RP; ++j) bx[j] = rects[j];
-
     const int nv = *pts.n_valid;
     const int c0 = blockIdx.y * chunk;
     const int c1 = min(c0 + chunk, nv);
-    float best = INFINITY;
-    int besti = -1;
-    for (int t0 = c0; t0 < c1; t0 += DMIN_TILE) {
-        const int tn = min(DMIN_TILE, c1 - t0);
-        __syncthreads();
-        stage_points<MOVING>(lds, pts, t0, tn);
-        __syncthreads();
-        for (int i = 0; i < tn; ++i) {
-            float dx, dy;
-            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
-            const float px = __builtin_fmaf(q.z, dx, q.w * dy);
-            const float py = __builtin_fmaf(q.z, dy, -(q.w * dx));
-            float s = box_s(px, py, bx[0]);
-#pragma unroll
-            for (int j = 1; j < RP; ++j) s = fminf(s, box_s(px, py, bx[j]));
-            if (ARGMIN) {
-                if (s < best) {
-                    best = s;
-                    besti = t0 + i;
-                }
-            } else {
-                best = fminf(best, s);
-            }
-        }
-    }
+    float best;
+    int besti;
+    dmin_rect_range<RP, MOVING, ARGMIN>(q, tau, pts, c0, c1, rects, lds, best, besti);
     if (live) {
         const size_t o = static_cast<size_t>(blockIdx.y) * npose + g;
         part[o] = best;
@@ -365,16 +194,17 @@ hipError_t launch_rect_t(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t
 }
 
 template <int P>
-hipError_t launch_kind(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
-    const bool mv = L.pts.vx != nullptr;
-    if (L.kind == 0) {
-        if (mv) return L.argmin ? launch_poly_t<P, true, true>(L, grid, lds, s)
-                                : launch_poly_t<P, true, false>(L, grid, lds, s);
-        return L.argmin ? launch_poly_t<P, false, true>(L, grid, lds, s)
-                        : launch_poly_t<P, false, false>(L, grid, lds, s);
-    }
-    if (mv) return L.argmin ? launch_rect_t<P, true, true>(L, grid, lds, s)
-                            : launch_rect_t<P, true, false>(L, grid, lds, s);
+hipError_t launch_poly(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
+    if (L.pts.vx) return L.argmin ? launch_poly_t<P, true, true>(L, grid, lds, s)
+                                  : launch_poly_t<P, true, false>(L, grid, lds, s);
+    return L.argmin ? launch_poly_t<P, false, true>(L, grid, lds, s)
+                    : launch_poly_t<P, false, false>(L, grid, lds, s);
+}
+
+template <int P>
+hipError_t launch_rect(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
+    if (L.pts.vx) return L.argmin ? launch_rect_t<P, true, true>(L, grid, lds, s)
+                                  : launch_rect_t<P, true, false>(L, grid, lds, s);
     return L.argmin ? launch_rect_t<P, false, true>(L, grid, lds, s)
                     : launch_rect_t<P, false, false>(L, grid, lds, s);
 }
@@ -394,28 +224,28 @@ hipError_t launch_dmin(const DminLaunch& L, hipStream_t s) {
     const size_t lds = static_cast<size_t>(DMIN_TILE) * (L.pts.vx ? 16 : 8);
     if (L.kind == 0) {
         switch (L.padded) {
-        case 4: return launch_kind<4>(L, grid, lds, s);
-        case 8: return launch_kind<8>(L, grid, lds, s);
-        case 12: return launch_kind<12>(L, grid, lds, s);
-        case 16: return launch_kind<16>(L, grid, lds, s);
-        case 20: return launch_kind<20>(L, grid, lds, s);
-        case 24: return launch_kind<24>(L, grid, lds, s);
-        case 28: return launch_kind<28>(L, grid, lds, s);
-        case 32: return launch_kind<32>(L, grid, lds, s);
+        case 4: return launch_poly<4>(L, grid, lds, s);
+        case 8: return launch_poly<8>(L, grid, lds, s);
+        case 12: return launch_poly<12>(L, grid, lds, s);
+        case 16: return launch_poly<16>(L, grid, lds, s);
+        case 20: return launch_poly<20>(L, grid, lds, s);
+        case 24: return launch_poly<24>(L, grid, lds, s);
+        case 28: return launch_poly<28>(L, grid, lds, s);
+        case 32: return launch_poly<32>(L, grid, lds, s);
         default: return hipErrorInvalidValue;
         }
     }
     switch (L.padded) {
-    case 1: return launch_kind<1>(L, grid, lds, s);
-    case 2: return launch_kind<2>(L, grid, lds, s);
-    case 3: return launch_kind<3>(L, grid, lds, s);
-    case 4: return launch_kind<4>(L, grid, lds, s);
-    case 6: return launch_kind<6>(L, grid, lds, s);
-    case 8: return launch_kind<8>(L, grid, lds, s);
-    case 12: return launch_kind<12>(L, grid, lds, s);
-    case 16: return launch_kind<16>(L, grid, lds, s);
-    case 24: return launch_kind<24>(L, grid, lds, s);
-    case 32: return launch_kind<32>(L, grid, lds, s);
+    case 1: return launch_rect<1>(L, grid, lds, s);
+    case 2: return launch_rect<2>(L, grid, lds, s);
+    case 3: return launch_rect<3>(L, grid, lds, s);
+    case 4: return launch_rect<4>(L, grid, lds, s);
+    case 6: return launch_rect<6>(L, grid, lds, s);
+    case 8: return launch_rect<8>(L, grid, lds, s);
+    case 12: return launch_rect<12>(L, grid, lds, s);
+    case 16: return launch_rect<16>(L, grid, lds, s);
+    case 24: return launch_rect<24>(L, grid, lds, s);
+    case 32: return launch_rect<32>(L, grid, lds, s);
     default: return hipErrorInvalidValue;
     }
 }

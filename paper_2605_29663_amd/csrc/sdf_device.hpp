@@ -1,0 +1,236 @@
+// Device building blocks of the fused rollout-frame transform + exact
+// signed distance + min-over-points stage, shared by the single-scene
+// kernels and the batched persistent kernel.
+//
+// Paper: Section "Signed Distance Evaluation" (rollout-frame transform, box
+// distance, polygon distance with ray-casting sign) and Section "Batched
+// Rollout and Distance Computation" (K x T x N queries, masked min).
+//
+// Mapping on gfx950 (wave64, VALU-bound): one lane = one pose (rollout r,
+// horizon h).  The footprint is rotated into the lane's frame once per work
+// item (7 registers per polygon edge); every obstacle point is broadcast to
+// all lanes from LDS, so the inner loop is pure per-lane VALU work with no
+// cross-lane traffic, and the min over points is a private running minimum.
+// Distances are kept squared and signed, s = sign(d) d^2 (monotone in d), so
+// one square root per pose replaces one per (point, edge).
+#pragma once
+#include "kernels.hpp"
+
+namespace emppi {
+
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
+// One polygon edge against the point (dx, dy) in a frame where the edge runs
+// from (X, Y) to (X + EX, Y + EY): squared point-to-segment distance with the
+// clipped projection t = clamp(w . e / |e|^2, 0, 1) (SX, SY = e / |e|^2), and
+// the ray-casting quantities "vertex above the point" (wy < 0) and "crossing
+// right of the point" (wx < wy * EX / EY, SL = EX / EY).
+struct EdgeEval {
+    float d2;
+    bool above;
+    bool right;
+};
+
+__device__ __forceinline__ EdgeEval edge_eval(float dx, float dy, float X, float Y, float EX,
+                                              float EY, float SX, float SY, float SL) {
+    const float wx = dx - X, wy = dy - Y;
+    const float t = clamp01(__builtin_fmaf(wy, SY, wx * SX));
+    const float rx = __builtin_fmaf(-t, EX, wx);
+    const float ry = __builtin_fmaf(-t, EY, wy);
+    EdgeEval e;
+    e.d2 = __builtin_fmaf(ry, ry, rx * rx);
+    e.above = wy < 0.0f;
+    e.right = wx < wy * SL;
+    return e;
+}
+
+// Signed squared distance of one box (centre c, half extents h) to the
+// body-frame point (px, py): with a = |p - c| - h, i = max(a_x, a_y) and
+// j = max(min(a_x, a_y), 0), sign(d) d^2 = i |i| + j^2, which is
+// |max(a,0)|^2 outside and -(max(a_x, a_y))^2 inside (the box formula).
+__device__ __forceinline__ float box_s(float px, float py, float4 b) {
+    const float ax = fabsf(px - b.x) - b.z;
+    const float ay = fabsf(py - b.y) - b.w;
+    const float i = fmaxf(ax, ay);
+    const float j = fmaxf(fminf(ax, ay), 0.0f);
+    return __builtin_fmaf(j, j, i * fabsf(i));
+}
+
+__device__ __forceinline__ float pose_tau(const PoseTime& pt, int g) {
+    const int h = (g / pt.div) % pt.mod;
+    return static_cast<float>(h + pt.off) * pt.dt;
+}
+
+__device__ __forceinline__ float signed_sqrt(float s) {
+    return s < 0.0f ? -__builtin_sqrtf(-s) : __builtin_sqrtf(s);
+}
+
+// Stage points [t0, t0 + tn) of the compacted set into LDS: (x, y) pairs for
+// static sets, (x, y, vx, vy) for moving ones.
+template <bool MOVING>
+__device__ __forceinline__ void stage_points(float* lds, const PointArgs& pts, int t0, int tn) {
+    if (MOVING) {
+        float4* l4 = reinterpret_cast<float4*>(lds);
+        for (int i = threadIdx.x; i < tn; i += blockDim.x)
+            l4[i] = make_float4(pts.x[t0 + i], pts.y[t0 + i], pts.vx[t0 + i], pts.vy[t0 + i]);
+    } else {
+        float2* l2 = reinterpret_cast<float2*>(lds);
+        for (int i = threadIdx.x; i < tn; i += blockDim.x)
+            l2[i] = make_float2(pts.x[t0 + i], pts.y[t0 + i]);
+    }
+}
+
+// Point i of the staged tile at time tau, relative to the pose position.
+template <bool MOVING>
+__device__ __forceinline__ void point_rel(const float* lds, int i, float tau, float qx, float qy,
+                                          float& dx, float& dy) {
+    if (MOVING) {
+        const float4 o = reinterpret_cast<const float4*>(lds)[i];
+        dx = __builtin_fmaf(o.z, tau, o.x) - qx;
+        dy = __builtin_fmaf(o.w, tau, o.y) - qy;
+    } else {
+        const float2 o = reinterpret_cast<const float2*>(lds)[i];
+        dx = o.x - qx;
+        dy = o.y - qy;
+    }
+}
+
+// Running min (and lowest-index argmin: points arrive in increasing index).
+template <bool ARGMIN>
+__device__ __forceinline__ void take(float s, int i, float& best, int& besti) {
+    if (ARGMIN) {
+        if (s < best) {
+            best = s;
+            besti = i;
+        }
+    } else {
+        best = fminf(best, s);
+    }
+}
+
+// Footprint of BP (padded) vertices rotated into the frame of pose q:
+// centred at the pose, aligned with the planning frame.  Padding repeats
+// vertex 0, giving zero-length edges (inverse squared length 0) that never
+// change the min and never straddle the ray.
+template <int BP>
+struct PolyFrame {
+    float X[BP], Y[BP], EX[BP], EY[BP], SX[BP], SY[BP], SL[BP];
+
+    __device__ __forceinline__ void init(const float2* __restrict__ verts, float c, float s) {
+#pragma unroll
+        for (int b = 0; b < BP; ++b) {
+            const float2 v = verts[b];
+            X[b] = __builtin_fmaf(c, v.x, -(s * v.y));
+            Y[b] = __builtin_fmaf(s, v.x, c * v.y);
+        }
+#pragma unroll
+        for (int b = 0; b < BP; ++b) {
+            const int bn = (b + 1) % BP;
+            EX[b] = X[bn] - X[b];
+            EY[b] = Y[bn] - Y[b];
+            const float l2 = __builtin_fmaf(EX[b], EX[b], EY[b] * EY[b]);
+            const float inv = l2 > 0.0f ? 1.0f / l2 : 0.0f;
+            SX[b] = EX[b] * inv;
+            SY[b] = EY[b] * inv;
+            SL[b] = EY[b] != 0.0f ? EX[b] / EY[b] : 0.0f;
+        }
+    }
+
+    // sign(d) d^2 of the point (dx, dy), given relative to the pose position.
+    __device__ __forceinline__ float eval(float dx, float dy) const {
+        EdgeEval e = edge_eval(dx, dy, X[0], Y[0], EX[0], EY[0], SX[0], SY[0], SL[0]);
+        float m = e.d2;
+        const bool above0 = e.above;
+        bool above = e.above, right = e.right, odd = false;
+#pragma unroll
+        for (int b = 1; b < BP; ++b) {
+            e = edge_eval(dx, dy, X[b], Y[b], EX[b], EY[b], SX[b], SY[b], SL[b]);
+            m = fminf(m, e.d2);
+            odd ^= (above != e.above) & right;
+            above = e.above;
+            right = e.right;
+        }
+        odd ^= (above != above0) & right;
+        return odd ? -m : m;
+    }
+};
+
+// Min over the valid points [c0, c1) of the signed squared distance to the
+// polygon for the pose (q, tau) held by this lane.  All threads of the
+// workgroup must call it (LDS staging uses barriers).
+template <int BP, bool MOVING, bool ARGMIN>
+__device__ __forceinline__ void dmin_poly_range(float4 q, float tau, const PointArgs& pts, int c0,
+                                                int c1, const float2* __restrict__ verts,
+                                                float* lds, float& best, int& besti) {
+    PolyFrame<BP> F;
+    F.init(verts, q.z, q.w);
+    best = INFINITY;
+    besti = -1;
+    for (int t0 = c0; t0 < c1; t0 += DMIN_TILE) {
+        const int tn = min(DMIN_TILE, c1 - t0);
+        __syncthreads();
+        stage_points<MOVING>(lds, pts, t0, tn);
+        __syncthreads();
+        int i = 0;
+        if (BP <= 20) {  // two points per iteration while registers allow
+            for (; i + 2 <= tn; i += 2) {
+                float dx0, dy0, dx1, dy1;
+                point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
+                point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
+                const float s0 = F.eval(dx0, dy0);
+                const float s1 = F.eval(dx1, dy1);
+                take<ARGMIN>(s0, t0 + i, best, besti);
+                take<ARGMIN>(s1, t0 + i + 1, best, besti);
+            }
+        }
+        for (; i < tn; ++i) {
+            float dx, dy;
+            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
+            take<ARGMIN>(F.eval(dx, dy), t0 + i, best, besti);
+        }
+    }
+}
+
+// Same for the rectangle cover: points rotated into the body frame,
+// p = R(theta)^T (o - t), then the min over the RP (padded) boxes.
+template <int RP, bool MOVING, bool ARGMIN>
+__device__ __forceinline__ void dmin_rect_range(float4 q, float tau, const PointArgs& pts, int c0,
+                                                int c1, const float4* __restrict__ rects,
+                                                float* lds, float& best, int& besti) {
+    float4 bx[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) bx[j] = rects[j];
+    best = INFINITY;
+    besti = -1;
+    auto eval = [&](float dx, float dy) {
+        const float px = __builtin_fmaf(q.z, dx, q.w * dy);
+        const float py = __builtin_fmaf(q.z, dy, -(q.w * dx));
+        float s = box_s(px, py, bx[0]);
+#pragma unroll
+        for (int j = 1; j < RP; ++j) s = fminf(s, box_s(px, py, bx[j]));
+        return s;
+    };
+    for (int t0 = c0; t0 < c1; t0 += DMIN_TILE) {
+        const int tn = min(DMIN_TILE, c1 - t0);
+        __syncthreads();
+        stage_points<MOVING>(lds, pts, t0, tn);
+        __syncthreads();
+        int i = 0;
+        for (; i + 2 <= tn; i += 2) {
+            float dx0, dy0, dx1, dy1;
+            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
+            point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
+            const float s0 = eval(dx0, dy0);
+            const float s1 = eval(dx1, dy1);
+            take<ARGMIN>(s0, t0 + i, best, besti);
+            take<ARGMIN>(s1, t0 + i + 1, best, besti);
+        }
+        if (i < tn) {
+            float dx, dy;
+            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
+            take<ARGMIN>(eval(dx, dy), t0 + i, best, besti);
+        }
+    }
+}
+
+}  // namespace emppi

@@ -1,0 +1,286 @@
+// Device building blocks of the sampling / rollout, cost, update, nominal and
+// validation stages (Algorithm 1 steps 1, 2-3, 4), shared by the
+// single-scene kernels and the batched ones.  Every reduction has a fixed
+// order, so a scene gives bit-identical results whether it runs alone or in
+// a batch, eagerly or from a captured graph.
+#pragma once
+#include "devmath.hpp"
+#include "kernels.hpp"
+
+namespace emppi {
+
+constexpr int ROLL_HCHUNK = 16;    // horizon steps of controls staged in LDS per chunk
+constexpr int COST_THREADS = 1024; // 64 rollouts x 16 horizon groups
+constexpr int FIN_THREADS = 1024;  // 128 poses x 8 chunk groups
+
+// One forward-Euler step q_{h+1} = q_h + F_m(q_h, u_h) dt (Section "Robot
+// Kinematic Models") in the fixed single-precision sequence; (s, c) =
+// sin/cos of theta_h.  "a += b dt" is one fma(b, dt, a).
+__device__ __forceinline__ void euler_step(int model, const float u[3], float dt, float L, float s,
+                                           float c, float& x, float& y, float& th) {
+    switch (model) {
+    case 0:  // unicycle (v, omega)
+        x = __builtin_fmaf(u[0] * c, dt, x);
+        y = __builtin_fmaf(u[0] * s, dt, y);
+        th = __builtin_fmaf(u[1], dt, th);
+        break;
+    case 1: {  // Ackermann (v, delta): theta' = v tan(delta) / L
+        const float w = (u[0] * seq_tan(u[1])) / L;
+        x = __builtin_fmaf(u[0] * c, dt, x);
+        y = __builtin_fmaf(u[0] * s, dt, y);
+        th = __builtin_fmaf(w, dt, th);
+        break;
+    }
+    case 2: {  // omni (vx, vy, omega)
+        const float xd = __builtin_fmaf(u[0], c, -(u[1] * s));
+        const float yd = __builtin_fmaf(u[0], s, u[1] * c);
+        x = __builtin_fmaf(xd, dt, x);
+        y = __builtin_fmaf(yd, dt, y);
+        th = __builtin_fmaf(u[2], dt, th);
+        break;
+    }
+    case 3:  // spin in place (omega)
+        th = __builtin_fmaf(u[0], dt, th);
+        break;
+    default:  // parallel (v_para)
+        x = __builtin_fmaf(-(u[0] * s), dt, x);
+        y = __builtin_fmaf(u[0] * c, dt, y);
+        break;
+    }
+}
+
+// Task + control terms of one scored state (the obstacle term is added once
+// the signed distances exist).
+__device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py, const float u[3]) {
+    const float gx = px - P.goal[0], gy = py - P.goal[1];
+    float v = P.w_goal * __builtin_sqrtf(gx * gx + gy * gy);
+    for (int c = 0; c < P.nu; ++c) v += P.w_ctrl[c] * (u[c] * u[c]);
+    return v;
+}
+
+// Sampling + rollouts of rollouts [r0, r0 + 64) (Algorithm 1 step 1).  For
+// each chunk of horizon steps, the whole workgroup draws the noise of the
+// 64 x chunk (r, h) pairs in parallel (sampled controls go to LDS), then one
+// wave integrates the 64 rollouts through the chunk.  lds: 3 * 64 *
+// ROLL_HCHUNK floats.
+__device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __restrict__ U,
+                                              const RolloutOut& o, int r0, float* lds) {
+    const int T = P.T, nu = P.nu, Kpad = P.Kpad;
+    const int r = r0 + static_cast<int>(threadIdx.x);
+    const bool live = threadIdx.x < WAVE && r < P.K;
+    float x = P.q0[0], y = P.q0[1], th = P.q0[2], s = 0.f, c = 1.f, jb = 0.0f;
+    if (threadIdx.x < WAVE) seq_sincos(th, s, c);
+    for (int h0 = 0; h0 < T; h0 += ROLL_HCHUNK) {
+        const int hn = min(ROLL_HCHUNK, T - h0);
+        for (int p = threadIdx.x; p < WAVE * hn; p += blockDim.x) {
+            const int rl = p & (WAVE - 1), hh = p / WAVE, h = h0 + hh, rr = r0 + rl;
+            if (rr >= P.K) continue;
+            float z[4];
+            normals4(P.seed, P.step, static_cast<uint32_t>(rr), static_cast<uint32_t>(h), P.stream, z);
+            for (int k = 0; k < nu; ++k) {
+                const float base = U[h * nu + k];
+                float v = base + P.sigma[k] * z[k];
+                v = fmaxf(v, P.umin[k]);
+                v = fminf(v, P.umax[k]);
+                const float e = v - base;
+                lds[(hh * 3 + k) * WAVE + rl] = v;
+                o.eps_ws[(h * nu + k) * Kpad + rr] = e;
+                const size_t d = (static_cast<size_t>(rr) * T + h) * nu + k;
+                if (o.diag_eps) o.diag_eps[d] = e;
+                if (o.diag_u) o.diag_u[d] = v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < WAVE) {
+            for (int hh = 0; hh < hn; ++hh) {
+                const int h = h0 + hh;
+                float u[3] = {0.f, 0.f, 0.f};
+                if (live)
+                    for (int k = 0; k < nu; ++k) u[k] = lds[(hh * 3 + k) * WAVE + threadIdx.x];
+                float4 pose = make_float4(x, y, c, s);
+                euler_step(P.model, u, P.dt, P.wheelbase, s, c, x, y, th);
+                seq_sincos(th, s, c);
+                if (P.state_offset) pose = make_float4(x, y, c, s);
+                o.poses[h * Kpad + r] = pose;
+                if (o.diag_poses && live) {
+                    float* dp = o.diag_poses + (static_cast<size_t>(r) * T + h) * 4;
+                    dp[0] = pose.x;
+                    dp[1] = pose.y;
+                    dp[2] = pose.z;
+                    dp[3] = pose.w;
+                }
+                jb += task_ctrl(P, pose.x, pose.y, u);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < WAVE) o.jbase[r] = jb;
+}
+
+// J~ of rollouts [r0, r0 + 64) (Algorithm 1 steps 2-3): lane l, group q of
+// the 1024 threads merges the chunk minima of (r0 + l, h) for h = q, q + 16,
+// ..., adds the obstacle penalties and the unsafe flag; the 16 partial sums
+// are added in index order.  lds: 2 * 1024 words.
+__device__ __forceinline__ void cost_block(const StepArgs& P, const float* __restrict__ part,
+                                           const int* __restrict__ part_idx, int nchunk,
+                                           const float* __restrict__ jbase, float* __restrict__ jt,
+                                           float* __restrict__ diag_dmin,
+                                           int* __restrict__ diag_argmin, int r0, float* lds) {
+    const int lane = threadIdx.x & (WAVE - 1), grp = threadIdx.x / WAVE;
+    const int ngrp = blockDim.x / WAVE;
+    const int r = r0 + lane;
+    const size_t npose = static_cast<size_t>(P.T) * P.Kpad;
+    float J = 0.0f;
+    int chi = 0;
+    if (r < P.K) {
+        for (int h = grp; h < P.T; h += ngrp) {
+            const size_t g = static_cast<size_t>(h) * P.Kpad + r;
+            float sq = part[g];
+            int idx = part_idx ? part_idx[g] : -1;
+            for (int k = 1; k < nchunk; ++k) {
+                const float v = part[k * npose + g];
+                if (v < sq) {
+                    sq = v;
+                    if (part_idx) idx = part_idx[k * npose + g];
+                }
+            }
+            const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
+            const float gap = fmaxf(P.d_safe - d, 0.0f);
+            J += (d < 0.0f ? P.w_coll : 0.0f) + P.w_rep * (gap * gap);
+            chi |= (d < P.d_safe) ? 1 : 0;
+            if (diag_dmin) diag_dmin[static_cast<size_t>(r) * P.T + h] = d;
+            if (diag_argmin) diag_argmin[static_cast<size_t>(r) * P.T + h] = idx;
+        }
+    }
+    float* sJ = lds;
+    int* sC = reinterpret_cast<int*>(lds + COST_THREADS);
+    sJ[threadIdx.x] = J;
+    sC[threadIdx.x] = chi;
+    __syncthreads();
+    if (grp == 0 && r < P.Kpad) {
+        if (r >= P.K) {
+            jt[r] = INFINITY;
+        } else {
+            float acc = jbase[r];
+            int any = 0;
+            for (int q = 0; q < ngrp; ++q) {
+                acc += sJ[q * WAVE + lane];
+                any |= sC[q * WAVE + lane];
+            }
+            jt[r] = acc + (any ? P.w_inf : 0.0f);
+        }
+    }
+}
+
+// Deterministic block reductions (fixed butterfly within a wave, waves
+// combined in index order).  sh: 16 floats.
+template <typename Op>
+__device__ __forceinline__ float block_reduce(float v, float* sh, Op op) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    float r = sh[0];
+    for (int w = 1; w < static_cast<int>(blockDim.x / WAVE); ++w) r = op(r, sh[w]);
+    return r;
+}
+
+// Horizon step h of the path-integral update (Algorithm 1 step 3):
+// beta = min J~, omega = exp(-(J~ - beta)/lambda), U_h += (sum omega eps_h) /
+// (sum omega).  256 threads; every (scene, h) workgroup computes the same beta
+// and normaliser in the same order.
+__device__ __forceinline__ void update_block(const StepArgs& P, const float* __restrict__ jt,
+                                             const float* __restrict__ eps_ws,
+                                             const float* __restrict__ U, float* __restrict__ Unew,
+                                             float* __restrict__ diag_w, int h, float* sh) {
+    const int Kpad = P.Kpad, nu = P.nu;
+    float b = INFINITY;
+    for (int r = threadIdx.x; r < Kpad; r += blockDim.x) b = fminf(b, jt[r]);
+    const float beta = block_reduce(b, sh, [](float a, float c) { return fminf(a, c); });
+    float z = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+    const float* e0 = eps_ws + (h * nu) * Kpad;
+    for (int r = threadIdx.x; r < Kpad; r += blockDim.x) {
+        const float w = expf((beta - jt[r]) / P.lambda);
+        z += w;
+        n0 += w * e0[r];
+        if (nu > 1) n1 += w * e0[Kpad + r];
+        if (nu > 2) n2 += w * e0[2 * Kpad + r];
+    }
+    auto add = [](float a, float c) { return a + c; };
+    const float Z = block_reduce(z, sh, add);
+    const float N0 = block_reduce(n0, sh, add);
+    const float N1 = nu > 1 ? block_reduce(n1, sh, add) : 0.f;
+    const float N2 = nu > 2 ? block_reduce(n2, sh, add) : 0.f;
+    if (threadIdx.x == 0) {
+        Unew[h * nu] = U[h * nu] + N0 / Z;
+        if (nu > 1) Unew[h * nu + 1] = U[h * nu + 1] + N1 / Z;
+        if (nu > 2) Unew[h * nu + 2] = U[h * nu + 2] + N2 / Z;
+    }
+    if (diag_w && h == 0)
+        for (int r = threadIdx.x; r < P.K; r += blockDim.x)
+            diag_w[r] = expf((beta - jt[r]) / P.lambda) / Z;
+}
+
+// Nominal trajectory of the updated sequence (Algorithm 1 step 4) in the same
+// single-precision sequence as the sampled rollouts.  The sequence is first
+// copied to LDS (lds: 3 * MPPI_MAX_T floats), then lane 0 integrates.
+__device__ __forceinline__ void nominal_block(const StepArgs& P, const float* __restrict__ Unew,
+                                              float4* __restrict__ nom, float* lds) {
+    for (int k = threadIdx.x; k < P.T * P.nu; k += blockDim.x) lds[k] = Unew[k];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    float x = P.q0[0], y = P.q0[1], th = P.q0[2], s, c;
+    seq_sincos(th, s, c);
+    for (int h = 0; h < P.T; ++h) {
+        float u[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < P.nu; ++k) u[k] = lds[h * P.nu + k];
+        float4 pose = make_float4(x, y, c, s);
+        euler_step(P.model, u, P.dt, P.wheelbase, s, c, x, y, th);
+        seq_sincos(th, s, c);
+        if (P.state_offset) pose = make_float4(x, y, c, s);
+        nom[h] = pose;
+    }
+}
+
+// Validation and execution (Algorithm 1 step 4): valid iff every
+// d_nom >= d_safe; then u* = U_0 and U shifts left (last entry repeated),
+// else u* = 0 and U = 0.  out4 = (u*_0, u*_1, u*_2, valid).  1024 threads:
+// pose h = tid % 128 merges chunk group tid / 128 (min is exact, so any
+// grouping gives the same value).  lds: 1024 floats.
+__device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
+                                               const float* __restrict__ part_nom, int nchunk,
+                                               const float* __restrict__ Unew,
+                                               float* __restrict__ U, float* __restrict__ out4,
+                                               float* __restrict__ diag_unew,
+                                               float* __restrict__ diag_dnom, float* lds) {
+    const int T = P.T, nu = P.nu;
+    const int h = threadIdx.x % MPPI_MAX_T_DEV, grp = threadIdx.x / MPPI_MAX_T_DEV;
+    const int ngrp = blockDim.x / MPPI_MAX_T_DEV;
+    float sq = INFINITY;
+    if (validate && h < T)
+        for (int k = grp; k < nchunk; k += ngrp) sq = fminf(sq, part_nom[k * T + h]);
+    lds[threadIdx.x] = sq;
+    __syncthreads();
+    int bad = 0;
+    if (validate && grp == 0 && h < T) {
+        for (int q = 1; q < ngrp; ++q) sq = fminf(sq, lds[q * MPPI_MAX_T_DEV + h]);
+        const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
+        bad = !(d >= P.d_safe);
+        if (diag_dnom) diag_dnom[h] = d;
+    }
+    const int ok = !__syncthreads_or(bad);
+    if (grp == 0 && h < T) {
+        const int src = (h + 1 < T ? h + 1 : T - 1) * nu;
+        for (int k = 0; k < nu; ++k) {
+            if (diag_unew) diag_unew[h * nu + k] = Unew[h * nu + k];
+            U[h * nu + k] = ok ? Unew[src + k] : 0.0f;
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) out4[k] = (ok && k < nu) ? Unew[k] : 0.0f;
+        out4[3] = ok ? 1.0f : 0.0f;
+    }
+}
+
+}  // namespace emppi

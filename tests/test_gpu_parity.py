@@ -366,6 +366,35 @@ def test_step_deterministic(ctx, pkg):
         assert np.array_equal(o[3], outs[0][3])
 
 
+def test_step_bitwise_identical_across_tiles(ctx, pkg):
+    """Every tile shape (and the autotuner's pick) gives bit-identical outputs."""
+    import torch
+    prm, sc = _step_case("c2", K=256, N=2000, T=16)
+    _load_scene(ctx, pkg, prm, sc)
+    ref = None
+    shapes = [(0, 0), (64, 1), (64, 7), (128, 3), (256, 2), (256, 31)]
+    try:
+        for blk, nc in shapes:
+            ctx.mppi_set_tiles(blk, nc)
+            Ut = torch.zeros((prm["T"], prm["nu"]), device="cuda")
+            u, v, D = ctx.mppi_step(prm, np.zeros(3, np.float32), Ut, 3, 1, diag=True)
+            out = {k: _np(t) for k, t in D.items()}
+            out["U"] = _np(Ut)
+            if ref is None:
+                ref = out
+            for k in out:
+                assert np.array_equal(out[k], ref[k], equal_nan=True), (blk, nc, k)
+        ctx.mppi_set_tiles(0, 0)
+        blk, nc = ctx.mppi_autotune(prm, reps=1)
+        assert blk in (64, 128, 256) and nc >= 1
+        Ut = torch.zeros((prm["T"], prm["nu"]), device="cuda")
+        u, v, D = ctx.mppi_step(prm, np.zeros(3, np.float32), Ut, 3, 1, diag=True)
+        assert np.array_equal(_np(D["d_min"]), ref["d_min"])
+        assert np.array_equal(_np(Ut), ref["U"])
+    finally:
+        ctx.mppi_set_tiles(0, 0)
+
+
 # ------------------------------------------------------------- full sizes
 
 @pytest.mark.parametrize("name", ["c2", "c3"])
