@@ -233,6 +233,60 @@ MPPI_API int mppi_set_profiling(mppi_ctx ctx, int enable);
  * Synchronous.                                                             */
 MPPI_API int mppi_get_profile(mppi_ctx ctx, double* ms, long long* launches);
 
+/* ------------------------------------------------------------------------
+ * Batched step: many independent scenes of uneven size in one launch
+ * sequence.  Each scene is an existing context (its footprint and point set)
+ * plus its own mppi_params (model, K, T, costs may all differ).  The
+ * signed-distance stage of all scenes runs as one persistent kernel per
+ * register class pulling (scene, pose tile, point chunk) items from a
+ * longest-first queue; the whole cycle can be captured in one hipGraph and
+ * replayed.  Each scene's outputs are bit-identical to mppi_step on that
+ * scene's context with the same arguments.
+ * ------------------------------------------------------------------------ */
+typedef struct mppi_batch_s* mppi_batch;
+
+/* Create a batch over n contexts (host array `scenes`, all on one device,
+ * footprint and points already set) with per-scene parameters (host array
+ * `prms`, copied).  Work runs on `hip_stream`, which must not be the legacy
+ * NULL stream when graphs are used; NULL makes the batch create its own
+ * non-blocking stream.  The contexts must outlive the batch.  Errors:
+ * MPPI_E_ARG, MPPI_E_CAPACITY, MPPI_E_NO_FOOTPRINT, MPPI_E_HIP (message via
+ * mppi_batch_last_error(NULL)).                                             */
+MPPI_API int mppi_batch_create(mppi_batch* out, const mppi_ctx* scenes, const mppi_params* prms,
+                               int n, void* hip_stream);
+MPPI_API int mppi_batch_destroy(mppi_batch b);
+MPPI_API const char* mppi_batch_last_error(mppi_batch b);
+
+/* offsets (host, n+1 ints): scene s's nominal U_s (T_s x nu_s, row-major)
+ * lives at dU + offsets[s] in the packed array mppi_step_batched takes.     */
+MPPI_API int mppi_batch_u_offsets(mppi_batch b, int* offsets);
+
+/* Re-plan after set_points / set_footprint on any of the batch's contexts
+ * (a step refuses with MPPI_E_STATE until then).  Drops the captured graph. */
+MPPI_API int mppi_batch_refresh(mppi_batch b);
+
+/* One control cycle (Algorithm 1, as in mppi_step) of every scene.
+ * q0: host n x 3.  dU: device packed nominals (see mppi_batch_u_offsets),
+ * updated in place.  seeds, steps: host n.  u_out: host n x 3 (unused
+ * channels 0).  valid_out: host n, may be NULL.  use_graph != 0 replays the
+ * captured graph (captured on the first such call; arguments are refreshed
+ * by a host-to-device copy inside the graph, so dU, q0, seeds and steps may
+ * change between calls).  Synchronous.                                     */
+MPPI_API int mppi_step_batched(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
+                               const uint64_t* steps, float* u_out, int* valid_out, int use_graph);
+
+/* Tile autotuner of the batch: times the persistent signed-distance pass for
+ * queue items of 2^18 .. 2^26 point-primitive pairs (reps launches each, HIP
+ * events) and re-plans with the fastest.  *out_work_per_item (may be NULL)
+ * receives it.  Results do not depend on the choice.  Synchronous.         */
+MPPI_API int mppi_batch_autotune(mppi_batch b, int reps, double* out_work_per_item);
+
+/* Size of the current plan: queue items of the sampled-rollout pass and of
+ * the validation pass, and the target pairs per item.  Any pointer may be
+ * NULL.                                                                     */
+MPPI_API int mppi_batch_info(mppi_batch b, long long* items_main, long long* items_validation,
+                             double* work_per_item);
+
 #ifdef __cplusplus
 }
 #endif

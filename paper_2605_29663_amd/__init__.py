@@ -27,7 +27,10 @@ MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
            "set_footprint", "set_points",
            "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
-           "mppi_autotune", "mppi_set_tiles", "mppi_set_profiling", "mppi_get_profile")
+           "mppi_autotune", "mppi_set_tiles", "mppi_set_profiling", "mppi_get_profile",
+           "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
+           "mppi_batch_u_offsets", "mppi_batch_refresh", "mppi_step_batched",
+           "mppi_batch_autotune", "mppi_batch_info")
 
 
 class MppiError(RuntimeError):
@@ -85,8 +88,19 @@ def load():
     L.mppi_set_profiling.argtypes = [vp, i]
     L.mppi_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_longlong)]
+    L.mppi_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(MppiParams), i, vp]
+    L.mppi_batch_destroy.argtypes = [vp]
+    L.mppi_batch_last_error.argtypes = [vp]
+    L.mppi_batch_last_error.restype = ctypes.c_char_p
+    L.mppi_batch_u_offsets.argtypes = [vp, ctypes.POINTER(i)]
+    L.mppi_batch_refresh.argtypes = [vp]
+    L.mppi_step_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, i]
+    L.mppi_batch_autotune.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
+    L.mppi_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
+                                  ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
-        if name not in ("mppi_last_error",):
+        if name not in ("mppi_last_error", "mppi_batch_last_error"):
             getattr(L, name).restype = i
     _lib = L
     return L
@@ -273,3 +287,85 @@ class Context:
                                        u_out, ctypes.byref(valid),
                                        ctypes.byref(D) if D is not None else None))
         return np.array(u_out[:nu], dtype=np.float32), bool(valid.value), out
+
+
+class Batch:
+    """Batched step over several contexts (one scene each).
+
+    The batch runs on its own (non-default) torch stream, which waits for the
+    caller's current stream before every step.
+    """
+
+    def __init__(self, contexts, params_list):
+        if len(contexts) != len(params_list) or not contexts:
+            raise ValueError("one parameter set per context")
+        self.lib = load()
+        self.contexts = list(contexts)      # keep the contexts alive
+        self.params = (MppiParams * len(contexts))(*[make_params(p) for p in params_list])
+        self.n = len(contexts)
+        self.device = contexts[0].device
+        self.stream = torch.cuda.Stream(device=self.device)
+        handles = (ctypes.c_void_p * self.n)(*[c.h.value for c in contexts])
+        h = ctypes.c_void_p()
+        rc = self.lib.mppi_batch_create(ctypes.byref(h), handles, self.params, self.n,
+                                        ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.mppi_batch_last_error(None).decode())
+        self.h = h
+        off = (ctypes.c_int * (self.n + 1))()
+        self._check(self.lib.mppi_batch_u_offsets(self.h, off))
+        self.u_offsets = list(off)
+
+    def _check(self, rc):
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.mppi_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mppi_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mppi_batch_refresh(self):
+        self._check(self.lib.mppi_batch_refresh(self.h))
+
+    def mppi_batch_autotune(self, reps=3):
+        w = ctypes.c_double()
+        self._check(self.lib.mppi_batch_autotune(self.h, int(reps), ctypes.byref(w)))
+        return w.value
+
+    def mppi_batch_info(self):
+        a, b, w = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_double()
+        self._check(self.lib.mppi_batch_info(self.h, ctypes.byref(a), ctypes.byref(b),
+                                             ctypes.byref(w)))
+        return a.value, b.value, w.value
+
+    def new_nominals(self):
+        return torch.zeros(max(1, self.u_offsets[-1]), dtype=torch.float32, device=self.device)
+
+    def nominal(self, U, s):
+        p = self.params[s]
+        return U[self.u_offsets[s]:self.u_offsets[s + 1]].view(p.T, p.nu)
+
+    def mppi_step_batched(self, q0, U, seeds, steps, use_graph=True):
+        """q0 (n, 3); U packed device nominals (updated in place); seeds, steps (n,).
+        Returns (u_star (n, 3) ndarray, valid (n,) bool ndarray)."""
+        q = np.ascontiguousarray(np.asarray(q0, dtype=np.float32).reshape(self.n, 3))
+        sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(self.n))
+        st = np.ascontiguousarray(np.asarray(steps, dtype=np.uint64).reshape(self.n))
+        if not (U.is_cuda and U.dtype == torch.float32 and U.is_contiguous()):
+            raise TypeError("U must be a contiguous float32 CUDA tensor")
+        u_out = np.zeros((self.n, 3), dtype=np.float32)
+        valid = np.zeros(self.n, dtype=np.int32)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        vp = ctypes.c_void_p
+        self._check(self.lib.mppi_step_batched(
+            self.h, q.ctypes.data_as(vp), _ptr(U), sd.ctypes.data_as(vp), st.ctypes.data_as(vp),
+            u_out.ctypes.data_as(vp), valid.ctypes.data_as(vp), int(bool(use_graph))))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return u_out, valid.astype(bool)

@@ -15,313 +15,10 @@
 #include "../../include/exact_mppi.h"
 #include "kernels.hpp"
 
+#include "ctx.hpp"
+
 using namespace emppi;
-
-namespace {
-
-thread_local std::string g_create_error;
-
-// A growable device buffer owned by the context.
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-    hipError_t ensure(size_t bytes) {
-        if (bytes <= cap) return hipSuccess;
-        if (p) {
-            hipError_t e = hipFree(p);
-            if (e != hipSuccess) return e;
-            p = nullptr;
-            cap = 0;
-        }
-        const size_t want = std::max<size_t>(bytes, 256);
-        hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) cap = want;
-        return e;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-    template <typename T>
-    T* as() const {
-        return static_cast<T*>(p);
-    }
-};
-
-}  // namespace
-
-struct mppi_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-    // footprint: polygon (padded vertices + point-wise tables) and rectangle cover
-    bool has_poly = false, has_rect = false;
-    int B = 0, BP = 0, R = 0, RP = 0;
-    DevBuf poly_verts, poly_tab_a, poly_tab_b, rects;
-    // obstacle points (compacted)
-    int n_points = 0;
-    bool moving = false;
-    DevBuf px, py, pvx, pvy, pidx, n_valid;
-    // step workspaces
-    DevBuf eps_ws, poses_ws, jbase, jt, part, part_idx, unew, nom_poses, part_nom, out4;
-    float* h_out = nullptr;  // pinned
-    // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
-    std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
-    int force_block = 0, force_nchunk = 0;  // mppi_set_tiles
-    // profiling of the dominant launch
-    bool prof = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double prof_ms = 0.0;
-    long long prof_n = 0;
-};
-
-namespace {
-
-int fail(mppi_ctx ctx, int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (ctx)
-        ctx->err = buf;
-    else
-        g_create_error = buf;
-    return code;
-}
-
-#define HIP_TRY(ctx, expr)                                                                    \
-    do {                                                                                      \
-        hipError_t _e = (expr);                                                               \
-        if (_e != hipSuccess)                                                                 \
-            return fail((ctx), MPPI_E_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));    \
-    } while (0)
-
-// RAII guard that makes ctx->device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-// Proper intersection or touching of segments ab and cd (double precision).
-double orient2(const double* a, const double* b, const double* c) {
-    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
-}
-bool on_segment(const double* a, const double* b, const double* p) {
-    return std::min(a[0], b[0]) <= p[0] && p[0] <= std::max(a[0], b[0]) &&
-           std::min(a[1], b[1]) <= p[1] && p[1] <= std::max(a[1], b[1]);
-}
-bool segments_meet(const double* a, const double* b, const double* c, const double* d) {
-    const double o1 = orient2(a, b, c), o2 = orient2(a, b, d);
-    const double o3 = orient2(c, d, a), o4 = orient2(c, d, b);
-    if (((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0)))
-        return true;
-    if (o1 == 0 && on_segment(a, b, c)) return true;
-    if (o2 == 0 && on_segment(a, b, d)) return true;
-    if (o3 == 0 && on_segment(c, d, a)) return true;
-    if (o4 == 0 && on_segment(c, d, b)) return true;
-    return false;
-}
-
-// Simple-polygon check: finite, no zero-length edge, non-zero area, and no
-// two non-adjacent edges meeting (adjacent edges may only share their common
-// vertex: a fold-back onto the previous edge is rejected too).
-int check_polygon(mppi_ctx ctx, const std::vector<double>& v, int B) {
-    for (double x : v)
-        if (!std::isfinite(x)) return fail(ctx, MPPI_E_FOOTPRINT, "non-finite vertex coordinate");
-    double area2 = 0.0;
-    for (int b = 0; b < B; ++b) {
-        const double* p = &v[2 * b];
-        const double* q = &v[2 * ((b + 1) % B)];
-        if (p[0] == q[0] && p[1] == q[1])
-            return fail(ctx, MPPI_E_FOOTPRINT, "zero-length edge %d", b);
-        area2 += p[0] * q[1] - q[0] * p[1];
-    }
-    if (std::fabs(area2) * 0.5 < 1e-12) return fail(ctx, MPPI_E_FOOTPRINT, "polygon area below 1e-12");
-    for (int i = 0; i < B; ++i) {
-        const double* a = &v[2 * i];
-        const double* b = &v[2 * ((i + 1) % B)];
-        for (int j = i + 1; j < B; ++j) {
-            const double* c = &v[2 * j];
-            const double* d = &v[2 * ((j + 1) % B)];
-            const bool next = (j == i + 1), prev = ((j + 1) % B == i);
-            if (next || prev) {
-                // adjacent: collinear overlap beyond the shared vertex is a fold-back
-                const double* far = next ? d : c;          // the non-shared end of edge j
-                const double* far_i = next ? a : b;        // the non-shared end of edge i
-                const double* shared = next ? b : a;
-                if (orient2(a, b, far) == 0 && on_segment(a, b, far) &&
-                    !(far[0] == shared[0] && far[1] == shared[1]))
-                    return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d fold back", i, j);
-                if (orient2(c, d, far_i) == 0 && on_segment(c, d, far_i))
-                    return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d fold back", i, j);
-                continue;
-            }
-            if (segments_meet(a, b, c, d))
-                return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d touch or cross (not simple)", i, j);
-        }
-    }
-    return MPPI_OK;
-}
-
-bool valid_model(int model, int nu) {
-    switch (model) {
-    case MPPI_UNICYCLE:
-    case MPPI_ACKERMANN: return nu == 2;
-    case MPPI_OMNI: return nu == 3;
-    case MPPI_SPIN:
-    case MPPI_PARALLEL: return nu == 1;
-    default: return false;
-    }
-}
-
-int check_params(mppi_ctx ctx, const mppi_params* p) {
-    if (!p) return fail(ctx, MPPI_E_ARG, "params is NULL");
-    if (p->K < 1 || p->K > MPPI_MAX_K) return fail(ctx, MPPI_E_CAPACITY, "K=%d outside [1, %d]", p->K, MPPI_MAX_K);
-    if (p->T < 1 || p->T > MPPI_MAX_T) return fail(ctx, MPPI_E_CAPACITY, "T=%d outside [1, %d]", p->T, MPPI_MAX_T);
-    if (p->nu < 1 || p->nu > 3) return fail(ctx, MPPI_E_CAPACITY, "nu=%d outside [1, 3]", p->nu);
-    if (!valid_model(p->model, p->nu)) return fail(ctx, MPPI_E_ARG, "model %d does not take nu=%d", p->model, p->nu);
-    if (p->footprint_kind != MPPI_FP_POLYGON && p->footprint_kind != MPPI_FP_RECTS)
-        return fail(ctx, MPPI_E_ARG, "footprint_kind %d", p->footprint_kind);
-    if (!(p->dt > 0) || !(p->lambda > 0) || !std::isfinite(p->dt) || !std::isfinite(p->lambda))
-        return fail(ctx, MPPI_E_ARG, "dt and lambda must be positive and finite");
-    if (p->model == MPPI_ACKERMANN && !(p->wheelbase > 0))
-        return fail(ctx, MPPI_E_ARG, "wheelbase must be positive");
-    for (int c = 0; c < p->nu; ++c)
-        if (!(p->u_min[c] <= p->u_max[c]) || !(p->sigma[c] >= 0))
-            return fail(ctx, MPPI_E_ARG, "channel %d: need sigma >= 0 and u_min <= u_max", c);
-    if (p->footprint_kind == MPPI_FP_POLYGON && !ctx->has_poly)
-        return fail(ctx, MPPI_E_NO_FOOTPRINT, "no polygon footprint set");
-    if (p->footprint_kind == MPPI_FP_RECTS && !ctx->has_rect)
-        return fail(ctx, MPPI_E_NO_FOOTPRINT, "no rectangle cover set");
-    return MPPI_OK;
-}
-
-StepArgs make_args(const mppi_params* p, const float* q0, uint64_t seed, uint64_t step) {
-    StepArgs a{};
-    a.K = p->K;
-    a.Kpad = (p->K + WAVE - 1) / WAVE * WAVE;
-    a.T = p->T;
-    a.nu = p->nu;
-    a.model = p->model;
-    a.state_offset = p->state_offset ? 1 : 0;
-    a.dt = p->dt;
-    a.lambda = p->lambda;
-    a.wheelbase = p->wheelbase;
-    for (int c = 0; c < 3; ++c) {
-        const bool on = c < p->nu;
-        a.sigma[c] = on ? p->sigma[c] : 0.f;
-        a.umin[c] = on ? p->u_min[c] : 0.f;
-        a.umax[c] = on ? p->u_max[c] : 0.f;
-        a.w_ctrl[c] = on ? p->w_ctrl[c] : 0.f;
-        a.q0[c] = q0[c];
-    }
-    a.d_safe = p->d_safe;
-    a.w_coll = p->w_coll;
-    a.w_rep = p->w_rep;
-    a.w_inf = p->w_inf;
-    a.w_goal = p->w_goal;
-    a.goal[0] = p->goal[0];
-    a.goal[1] = p->goal[1];
-    a.seed = seed;
-    a.step = step;
-    a.stream = 0;
-    return a;
-}
-
-PointArgs point_args(mppi_ctx ctx) {
-    PointArgs pa;
-    pa.x = ctx->px.as<float>();
-    pa.y = ctx->py.as<float>();
-    pa.vx = ctx->moving ? ctx->pvx.as<float>() : nullptr;
-    pa.vy = ctx->moving ? ctx->pvy.as<float>() : nullptr;
-    pa.idx = ctx->pidx.as<int>();
-    pa.n_valid = ctx->n_valid.as<int>();
-    return pa;
-}
-
-// Waves per SIMD the fused kernel runs at (its register budget), used to
-// estimate how many workgroups are resident at once.
-int dmin_waves_per_simd(int kind, int padded) {
-    if (kind == 1) return 8;
-    return padded <= 8 ? 6 : padded <= 16 ? 4 : padded <= 20 ? 3 : 2;
-}
-
-// Default tile shape: chunks of at least 32 points, and a workgroup count
-// close to a whole number of "rounds" of resident workgroups so that the
-// last round is not a nearly empty tail (all workgroups do equal work).
-void choose_tiles(int kind, int padded, int npose, int n_points, int& block, int& nchunk, int& chunk) {
-    block = npose >= 4096 ? 256 : 64;
-    const int pose_blocks = std::max(1, (npose + block - 1) / block);
-    const int resident = 256 * 4 * dmin_waves_per_simd(kind, padded) / (block / WAVE);
-    const int max_chunks = std::max(1, n_points / 32);
-    int best_nc = 1;
-    double best_eff = -1.0;
-    for (int nc = 1; nc <= std::min(max_chunks, 4096); ++nc) {
-        const long long wgs = static_cast<long long>(pose_blocks) * nc;
-        const double rounds = static_cast<double>(wgs) / resident;
-        const double eff = rounds / std::ceil(rounds);      // fill of the last round
-        const double score = eff * std::min(1.0, rounds / 4.0);  // prefer >= 4 rounds
-        if (score > best_eff + 1e-9) {
-            best_eff = score;
-            best_nc = nc;
-        }
-        if (rounds > 16) break;
-    }
-    chunk = std::max(1, (n_points + best_nc - 1) / best_nc);
-    nchunk = std::max(1, (n_points + chunk - 1) / chunk);
-}
-
-int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind, bool argmin,
-             DevBuf& part, DevBuf* part_idx, int& nchunk_out, int force_block = 0,
-             int force_nchunk = 0) {
-    const int padded = kind == 0 ? ctx->BP : ctx->RP;
-    int block, nchunk, chunk;
-    choose_tiles(kind, padded, npose, ctx->n_points, block, nchunk, chunk);
-    const auto it = ctx->tuned.find(std::make_tuple(kind, padded, ctx->moving ? 1 : 0, npose, ctx->n_points));
-    if (it != ctx->tuned.end()) {
-        block = it->second.first;
-        nchunk = it->second.second;
-    }
-    if (ctx->force_block) {
-        block = ctx->force_block;
-        nchunk = ctx->force_nchunk;
-    }
-    if (force_block) block = force_block;
-    if (force_nchunk) nchunk = force_nchunk;
-    chunk = std::max(1, (ctx->n_points + nchunk - 1) / nchunk);
-    nchunk = std::max(1, (ctx->n_points + chunk - 1) / chunk);
-    HIP_TRY(ctx, part.ensure(sizeof(float) * static_cast<size_t>(npose) * nchunk));
-    if (argmin) HIP_TRY(ctx, part_idx->ensure(sizeof(int) * static_cast<size_t>(npose) * nchunk));
-    DminLaunch L{};
-    L.poses = poses;
-    L.npose = npose;
-    L.pt = pt;
-    L.pts = point_args(ctx);
-    L.chunk = chunk;
-    L.nchunk = nchunk;
-    L.block = block;
-    L.kind = kind;
-    L.verts = ctx->poly_verts.as<float2>();
-    L.rects = ctx->rects.as<float4>();
-    L.padded = padded;
-    L.argmin = argmin;
-    L.part = part.as<float>();
-    L.part_idx = argmin ? part_idx->as<int>() : nullptr;
-    HIP_TRY(ctx, launch_dmin(L, ctx->stream));
-    nchunk_out = nchunk;
-    return MPPI_OK;
-}
-
-}  // namespace
+using namespace emppi_host;
 
 static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
                            float* deps, float* du);

@@ -1,0 +1,473 @@
+// C ABI of the batched multi-scene step (declared in include/exact_mppi.h):
+// planning of the longest-first work queue, workspaces, eager execution,
+// hipGraph capture and replay, and the tile autotuner of the batch.
+#include "ctx.hpp"
+
+using namespace emppi;
+using namespace emppi_host;
+
+struct mppi_batch_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int n = 0;
+    std::vector<mppi_ctx> scenes;
+    std::vector<mppi_params> prms;
+    std::vector<StepArgs> args;     // static part of each scene's step arguments
+    std::vector<int> u_off;         // offsets of the scenes' nominals in the packed array
+    // snapshot of what the plan was built from
+    std::vector<int> snap_n;
+    std::vector<const void*> snap_ptr;
+    // plan
+    double work_per_item = 0.0;     // target point-primitive pairs per queue item
+    std::vector<SceneBufs> bufs;
+    std::vector<SceneDmin> sdm;     // [pass][scene]
+    std::vector<DminItem> items[2][DMIN_CLASSES];  // [pass][register class]
+    std::vector<int2> blk_roll, blk_upd;
+    DevBuf arena, d_steps, d_bufs, d_sdm, d_items[2][DMIN_CLASSES], d_blk_roll, d_blk_upd, d_counters, d_out;
+    SceneStep* h_steps = nullptr;   // pinned
+    float* h_out = nullptr;         // pinned
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool planned = false;
+};
+
+namespace {
+
+int bfail(mppi_batch b, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b)
+        b->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define BHIP(b, expr)                                                                         \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            return bfail((b), MPPI_E_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));     \
+    } while (0)
+
+void drop_graph(mppi_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// The scene data the plan depends on: point count and buffer addresses.
+void snapshot(mppi_batch b) {
+    b->snap_n.clear();
+    b->snap_ptr.clear();
+    for (mppi_ctx c : b->scenes) {
+        b->snap_n.push_back(c->n_points);
+        b->snap_n.push_back(c->moving ? 1 : 0);
+        b->snap_n.push_back(c->BP * 100 + c->RP);
+        b->snap_ptr.push_back(c->px.p);
+        b->snap_ptr.push_back(c->pvx.p);
+        b->snap_ptr.push_back(c->poly_verts.p);
+        b->snap_ptr.push_back(c->rects.p);
+    }
+}
+
+bool snapshot_matches(mppi_batch b) {
+    size_t k = 0, m = 0;
+    for (mppi_ctx c : b->scenes) {
+        if (b->snap_n[k++] != c->n_points || b->snap_n[k++] != (c->moving ? 1 : 0) ||
+            b->snap_n[k++] != c->BP * 100 + c->RP)
+            return false;
+        if (b->snap_ptr[m++] != c->px.p || b->snap_ptr[m++] != c->pvx.p ||
+            b->snap_ptr[m++] != c->poly_verts.p || b->snap_ptr[m++] != c->rects.p)
+            return false;
+    }
+    return true;
+}
+
+// Build the work queue for a given target work per item, size and carve the
+// workspace arena, and upload the static tables.
+int plan(mppi_batch b, double work_per_item) {
+    drop_graph(b);
+    const int n = b->n;
+    b->work_per_item = work_per_item;
+    b->bufs.assign(n, SceneBufs{});
+    b->sdm.assign(2 * n, SceneDmin{});
+    for (auto& p : b->items)
+        for (auto& v : p) v.clear();
+    b->blk_roll.clear();
+    b->blk_upd.clear();
+    struct Cost {
+        double c;
+        DminItem it;
+    };
+    std::vector<Cost> q[2][DMIN_CLASSES];
+    // arena layout
+    std::vector<size_t> off(n * 9);
+    size_t total = 0;
+    std::vector<int> nchunk(n), chunk(n), nchunk_nom(n), chunk_nom(n);
+    for (int s = 0; s < n; ++s) {
+        const mppi_params& P = b->prms[s];
+        mppi_ctx c = b->scenes[s];
+        const int kind = P.footprint_kind;
+        const int padded = kind == 0 ? c->BP : c->RP;
+        const size_t Kpad = b->args[s].Kpad, T = P.T, nu = P.nu;
+        const int npts = std::max(c->n_points, 0);
+        // rollout pass: pose tiles of 256 lanes, chunks sized for the target work
+        const double per_point = 256.0 * padded;
+        int ck = static_cast<int>(std::max(32.0, std::min(static_cast<double>(std::max(npts, 1)),
+                                                          work_per_item / per_point)));
+        nchunk[s] = std::max(1, (npts + ck - 1) / ck);
+        chunk[s] = std::max(1, (npts + nchunk[s] - 1) / nchunk[s]);
+        // validation pass: the T poses in one 128-lane tile, small chunks
+        const int ckn = std::max(32, (npts + 63) / 64);
+        nchunk_nom[s] = std::max(1, (npts + ckn - 1) / ckn);
+        chunk_nom[s] = std::max(1, (npts + nchunk_nom[s] - 1) / nchunk_nom[s]);
+        const size_t sizes[9] = {sizeof(float) * T * nu * Kpad, sizeof(float4) * T * Kpad,
+                                 sizeof(float) * Kpad, sizeof(float) * Kpad,
+                                 sizeof(float) * nchunk[s] * T * Kpad, sizeof(float) * T * nu,
+                                 sizeof(float4) * T, sizeof(float) * nchunk_nom[s] * T, 0};
+        for (int k = 0; k < 9; ++k) {
+            off[s * 9 + k] = total;
+            total += align256(sizes[k]);
+        }
+    }
+    BHIP(b, b->arena.ensure(std::max<size_t>(total, 256)));
+    BHIP(b, b->d_out.ensure(sizeof(float) * 4 * n));
+    char* base = static_cast<char*>(b->arena.p);
+    for (int s = 0; s < n; ++s) {
+        const mppi_params& P = b->prms[s];
+        mppi_ctx c = b->scenes[s];
+        const int kind = P.footprint_kind;
+        const int padded = kind == 0 ? c->BP : c->RP;
+        const int Kpad = b->args[s].Kpad, T = P.T;
+        SceneBufs& B = b->bufs[s];
+        B.eps_ws = reinterpret_cast<float*>(base + off[s * 9 + 0]);
+        B.poses = reinterpret_cast<float4*>(base + off[s * 9 + 1]);
+        B.jbase = reinterpret_cast<float*>(base + off[s * 9 + 2]);
+        B.jt = reinterpret_cast<float*>(base + off[s * 9 + 3]);
+        B.part = reinterpret_cast<float*>(base + off[s * 9 + 4]);
+        B.nchunk = nchunk[s];
+        B.unew = reinterpret_cast<float*>(base + off[s * 9 + 5]);
+        B.nom = reinterpret_cast<float4*>(base + off[s * 9 + 6]);
+        B.part_nom = reinterpret_cast<float*>(base + off[s * 9 + 7]);
+        B.nchunk_nom = nchunk_nom[s];
+        B.out4 = b->d_out.as<float>() + 4 * s;
+        B.validate = P.validate ? 1 : 0;
+        const int cls = dmin_class(kind, padded);
+        for (int pass = 0; pass < 2; ++pass) {
+            SceneDmin& D = b->sdm[pass * n + s];
+            D.poses = pass == 0 ? B.poses : B.nom;
+            D.npose = pass == 0 ? T * Kpad : T;
+            D.pt = pass == 0 ? PoseTime{Kpad, T, b->args[s].state_offset, P.dt}
+                             : PoseTime{1, T, b->args[s].state_offset, P.dt};
+            D.pts = point_args(c);
+            D.chunk = pass == 0 ? chunk[s] : chunk_nom[s];
+            D.kind = kind;
+            D.padded = padded;
+            D.verts = c->poly_verts.as<float2>();
+            D.rects = c->rects.as<float4>();
+            D.part = pass == 0 ? B.part : B.part_nom;
+            if (pass == 1 && !P.validate) continue;
+            const int tile = pass == 0 ? 256 : 128;
+            const int nck = pass == 0 ? nchunk[s] : nchunk_nom[s];
+            for (int g0 = 0; g0 < D.npose; g0 += tile) {
+                const int live = std::min(tile, D.npose - g0);
+                for (int k = 0; k < nck; ++k) {
+                    const int len = std::max(0, std::min(D.chunk, c->n_points - k * D.chunk));
+                    q[pass][cls].push_back({static_cast<double>(live) * (len + 8) * padded,
+                                            DminItem{pass * n + s, g0, k, 0}});
+                }
+            }
+        }
+        for (int r0 = 0; r0 < Kpad; r0 += WAVE) b->blk_roll.push_back(make_int2(s, r0));
+        for (int h = 0; h < T; ++h) b->blk_upd.push_back(make_int2(s, h));
+    }
+    for (int pass = 0; pass < 2; ++pass)
+        for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
+            auto& v = q[pass][cls];
+            std::stable_sort(v.begin(), v.end(), [](const Cost& x, const Cost& y) { return x.c > y.c; });
+            for (auto& e : v) b->items[pass][cls].push_back(e.it);
+        }
+    // upload tables
+    BHIP(b, hipStreamSynchronize(b->stream));
+    BHIP(b, b->d_bufs.ensure(sizeof(SceneBufs) * n));
+    BHIP(b, b->d_sdm.ensure(sizeof(SceneDmin) * 2 * n));
+    BHIP(b, b->d_blk_roll.ensure(sizeof(int2) * std::max<size_t>(1, b->blk_roll.size())));
+    BHIP(b, b->d_blk_upd.ensure(sizeof(int2) * std::max<size_t>(1, b->blk_upd.size())));
+    BHIP(b, hipMemcpy(b->d_bufs.p, b->bufs.data(), sizeof(SceneBufs) * n, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_sdm.p, b->sdm.data(), sizeof(SceneDmin) * 2 * n, hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_blk_roll.p, b->blk_roll.data(), sizeof(int2) * b->blk_roll.size(),
+                      hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->d_blk_upd.p, b->blk_upd.data(), sizeof(int2) * b->blk_upd.size(),
+                      hipMemcpyHostToDevice));
+    for (int pass = 0; pass < 2; ++pass)
+        for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
+            auto& v = b->items[pass][cls];
+            BHIP(b, b->d_items[pass][cls].ensure(sizeof(DminItem) * std::max<size_t>(1, v.size())));
+            if (!v.empty())
+                BHIP(b, hipMemcpy(b->d_items[pass][cls].p, v.data(), sizeof(DminItem) * v.size(),
+                                  hipMemcpyHostToDevice));
+        }
+    snapshot(b);
+    b->planned = true;
+    return MPPI_OK;
+}
+
+int persistent_grid(int pass, int cls, size_t n_items) {
+    const int waves = dmin_persistent_waves(cls);
+    const int per_wg_waves = pass == 0 ? 4 : 2;  // 256- or 128-lane tiles
+    const int resident = 256 * 4 * waves / per_wg_waves;
+    return static_cast<int>(std::min<size_t>(n_items, static_cast<size_t>(resident)));
+}
+
+int launch_dmin_pass(mppi_batch b, int pass) {
+    for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
+        const auto& v = b->items[pass][cls];
+        if (v.empty()) continue;
+        BHIP(b, launch_dmin_persistent(cls, pass == 0 ? 256 : 128, persistent_grid(pass, cls, v.size()),
+                                       b->d_sdm.as<SceneDmin>(), b->d_items[pass][cls].as<DminItem>(),
+                                       static_cast<int>(v.size()), b->d_counters.as<int>() + DMIN_CLASSES * pass + cls,
+                                       b->stream));
+    }
+    return MPPI_OK;
+}
+
+// The whole batched cycle on b->stream (eager, or recorded into a graph).
+int enqueue_step(mppi_batch b) {
+    const int n = b->n;
+    SceneStep* ds = b->d_steps.as<SceneStep>();
+    SceneBufs* db = b->d_bufs.as<SceneBufs>();
+    BHIP(b, hipMemcpyAsync(b->d_steps.p, b->h_steps, sizeof(SceneStep) * n, hipMemcpyHostToDevice,
+                           b->stream));
+    BHIP(b, launch_batch_reset(b->d_counters.as<int>(), 2 * DMIN_CLASSES, b->stream));
+    BHIP(b, launch_rollout_batched(ds, db, b->d_blk_roll.as<int2>(),
+                                   static_cast<int>(b->blk_roll.size()), b->stream));
+    if (int rc = launch_dmin_pass(b, 0)) return rc;
+    BHIP(b, launch_cost_batched(ds, db, b->d_blk_roll.as<int2>(),
+                                static_cast<int>(b->blk_roll.size()), b->stream));
+    BHIP(b, launch_update_batched(ds, db, b->d_blk_upd.as<int2>(),
+                                  static_cast<int>(b->blk_upd.size()), b->stream));
+    BHIP(b, launch_nominal_batched(ds, db, n, b->stream));
+    if (int rc = launch_dmin_pass(b, 1)) return rc;
+    BHIP(b, launch_finalize_batched(ds, db, n, b->stream));
+    BHIP(b, hipMemcpyAsync(b->h_out, b->d_out.p, sizeof(float) * 4 * n, hipMemcpyDeviceToHost,
+                           b->stream));
+    return MPPI_OK;
+}
+
+int fill_steps(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
+               const uint64_t* steps) {
+    for (int s = 0; s < b->n; ++s) {
+        SceneStep& S = b->h_steps[s];
+        S.P = b->args[s];
+        for (int k = 0; k < 3; ++k) S.P.q0[k] = q0[3 * s + k];
+        S.P.seed = seeds[s];
+        S.P.step = steps[s];
+        S.U = dU + b->u_off[s];
+    }
+    return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mppi_batch_create(mppi_batch* out, const mppi_ctx* scenes, const mppi_params* prms, int n,
+                      void* hip_stream) {
+    if (!out) return bfail(nullptr, MPPI_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 4096 || !scenes || !prms) return bfail(nullptr, MPPI_E_ARG, "need 1..4096 scenes");
+    const int dev = scenes[0] ? scenes[0]->device : -1;
+    for (int s = 0; s < n; ++s) {
+        if (!scenes[s]) return bfail(nullptr, MPPI_E_ARG, "scene %d is NULL", s);
+        if (scenes[s]->device != dev) return bfail(nullptr, MPPI_E_ARG, "scenes on different devices");
+        if (int rc = check_params(scenes[s], &prms[s]))
+            return bfail(nullptr, rc, "scene %d: %s", s, scenes[s]->err.c_str());
+    }
+    mppi_batch b = new mppi_batch_s;
+    b->device = dev;
+    b->n = n;
+    b->scenes.assign(scenes, scenes + n);
+    b->prms.assign(prms, prms + n);
+    b->u_off.assign(n + 1, 0);
+    const float zero3[3] = {0.f, 0.f, 0.f};
+    for (int s = 0; s < n; ++s) {
+        b->args.push_back(make_args(&prms[s], zero3, 0, 0));
+        b->u_off[s + 1] = b->u_off[s] + prms[s].T * prms[s].nu;
+    }
+    DeviceGuard g(dev);
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        b->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        b->own_stream = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = b->d_steps.ensure(sizeof(SceneStep) * n);
+    if (e == hipSuccess) e = b->d_counters.ensure(sizeof(int) * 2 * DMIN_CLASSES);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_steps), sizeof(SceneStep) * n, 0);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(float) * 4 * n, 0);
+    if (e != hipSuccess) {
+        mppi_batch_destroy(b);
+        return bfail(nullptr, MPPI_E_HIP, "batch setup: %s", hipGetErrorString(e));
+    }
+    // default plan: about 2^22 point-primitive pairs per queue item
+    if (int rc = plan(b, 4194304.0)) {
+        std::string m = b->err;
+        mppi_batch_destroy(b);
+        return bfail(nullptr, rc, "%s", m.c_str());
+    }
+    *out = b;
+    return MPPI_OK;
+}
+
+int mppi_batch_destroy(mppi_batch b) {
+    if (!b) return MPPI_OK;
+    {
+        DeviceGuard g(b->device);
+        if (b->stream) (void)hipStreamSynchronize(b->stream);
+        drop_graph(b);
+        DevBuf* bufs[] = {&b->arena, &b->d_steps, &b->d_bufs, &b->d_sdm, &b->d_blk_roll,
+                          &b->d_blk_upd, &b->d_counters, &b->d_out};
+        for (DevBuf* x : bufs) x->release();
+        for (auto& pass : b->d_items)
+            for (DevBuf& x : pass) x.release();
+        if (b->h_steps) (void)hipHostFree(b->h_steps);
+        if (b->h_out) (void)hipHostFree(b->h_out);
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    }
+    delete b;
+    return MPPI_OK;
+}
+
+const char* mppi_batch_last_error(mppi_batch b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+int mppi_batch_u_offsets(mppi_batch b, int* offsets) {
+    if (!b || !offsets) return MPPI_E_ARG;
+    for (int s = 0; s <= b->n; ++s) offsets[s] = b->u_off[s];
+    return MPPI_OK;
+}
+
+int mppi_batch_refresh(mppi_batch b) {
+    if (!b) return MPPI_E_ARG;
+    DeviceGuard g(b->device);
+    return plan(b, b->work_per_item);
+}
+
+int mppi_step_batched(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
+                      const uint64_t* steps, float* u_out, int* valid_out, int use_graph) {
+    if (!b) return MPPI_E_ARG;
+    if (!q0 || !dU || !seeds || !steps || !u_out) return bfail(b, MPPI_E_ARG, "NULL argument");
+    if (!snapshot_matches(b))
+        return bfail(b, MPPI_E_STATE, "a scene's points or footprint changed: call mppi_batch_refresh");
+    DeviceGuard g(b->device);
+    fill_steps(b, q0, dU, seeds, steps);
+    if (use_graph) {
+        if (!b->exec) {
+            BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+            const int rc = enqueue_step(b);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            BHIP(b, e);
+            b->graph = graph;
+            BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        }
+        BHIP(b, hipGraphLaunch(b->exec, b->stream));
+    } else {
+        if (int rc = enqueue_step(b)) return rc;
+    }
+    BHIP(b, hipStreamSynchronize(b->stream));
+    for (int s = 0; s < b->n; ++s) {
+        for (int k = 0; k < b->prms[s].nu; ++k) u_out[3 * s + k] = b->h_out[4 * s + k];
+        for (int k = b->prms[s].nu; k < 3; ++k) u_out[3 * s + k] = 0.0f;
+        if (valid_out) valid_out[s] = b->h_out[4 * s + 3] != 0.0f;
+    }
+    return MPPI_OK;
+}
+
+int mppi_batch_autotune(mppi_batch b, int reps, double* out_work_per_item) {
+    if (!b) return MPPI_E_ARG;
+    if (reps < 1) reps = 3;
+    DeviceGuard g(b->device);
+    // poses of one cycle around zero nominals
+    std::vector<float> zeros(3 * b->n, 0.f);
+    std::vector<uint64_t> seeds(b->n, 0x7E57ull), stepv(b->n, 0);
+    DevBuf dU;
+    BHIP(b, dU.ensure(sizeof(float) * std::max(1, b->u_off[b->n])));
+    BHIP(b, hipMemsetAsync(dU.p, 0, sizeof(float) * std::max(1, b->u_off[b->n]), b->stream));
+    hipEvent_t e0, e1;
+    BHIP(b, hipEventCreate(&e0));
+    BHIP(b, hipEventCreate(&e1));
+    double best_w = b->work_per_item;
+    float best_ms = 1e30f;
+    int rc = MPPI_OK;
+    for (int lg = 18; lg <= 26 && rc == MPPI_OK; ++lg) {
+        const double w = std::ldexp(1.0, lg);
+        rc = plan(b, w);
+        if (rc) break;
+        fill_steps(b, zeros.data(), dU.as<float>(), seeds.data(), stepv.data());
+        hipError_t e = hipMemcpyAsync(b->d_steps.p, b->h_steps, sizeof(SceneStep) * b->n,
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = launch_rollout_batched(b->d_steps.as<SceneStep>(), b->d_bufs.as<SceneBufs>(),
+                                       b->d_blk_roll.as<int2>(), static_cast<int>(b->blk_roll.size()),
+                                       b->stream);
+        if (e != hipSuccess) {
+            rc = bfail(b, MPPI_E_HIP, "autotune: %s", hipGetErrorString(e));
+            break;
+        }
+        float ms_total = 0.f;
+        for (int k = 0; k <= reps && rc == MPPI_OK; ++k) {
+            e = launch_batch_reset(b->d_counters.as<int>(), 2 * DMIN_CLASSES, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess) rc = launch_dmin_pass(b, 0);
+            if (e == hipSuccess && rc == MPPI_OK) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess && rc == MPPI_OK) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess && rc == MPPI_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) rc = bfail(b, MPPI_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+            if (k > 0) ms_total += ms;  // the first launch is a warm-up
+        }
+        if (rc) break;
+        if (ms_total / reps < best_ms) {
+            best_ms = ms_total / reps;
+            best_w = w;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dU.release();
+    if (rc) return rc;
+    if (int r2 = plan(b, best_w)) return r2;
+    if (out_work_per_item) *out_work_per_item = best_w;
+    return MPPI_OK;
+}
+
+int mppi_batch_info(mppi_batch b, long long* items_main, long long* items_validation,
+                    double* work_per_item) {
+    if (!b) return MPPI_E_ARG;
+    long long m = 0, v = 0;
+    for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
+        m += static_cast<long long>(b->items[0][cls].size());
+        v += static_cast<long long>(b->items[1][cls].size());
+    }
+    if (items_main) *items_main = m;
+    if (items_validation) *items_validation = v;
+    if (work_per_item) *work_per_item = b->work_per_item;
+    return MPPI_OK;
+}
+
+}  // extern "C"

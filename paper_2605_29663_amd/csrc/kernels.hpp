@@ -92,4 +92,66 @@ hipError_t launch_finalize(const StepArgs& P, int validate, const float* part_no
                            const float* Unew, float* U, float* out4, float* diag_unew,
                            float* diag_dnom, hipStream_t s);
 
+// ---------------------------------------------------------------- batched path
+// Per-step arguments of one scene (refreshed by one host-to-device copy per
+// step, so a captured graph replays with new poses, seeds and nominals).
+struct SceneStep {
+    StepArgs P;
+    float* U;  // the scene's T x nu nominal (device), updated in place
+};
+
+// Static per-scene workspaces.
+struct SceneBufs {
+    float* eps_ws;   // [T][nu][Kpad]
+    float4* poses;   // [T][Kpad]
+    float* jbase;    // [Kpad]
+    float* jt;       // [Kpad]
+    float* part;     // [nchunk][T*Kpad]
+    int nchunk;
+    float* unew;     // [T][nu]
+    float4* nom;     // [T]
+    float* part_nom; // [nchunk_nom][T]
+    int nchunk_nom;
+    float* out4;     // 4 floats
+    int validate;    // run Algorithm 1 step 4 for this scene
+};
+
+// One (scene, pass) for the persistent signed-distance kernel.
+struct SceneDmin {
+    const float4* poses;
+    int npose;
+    PoseTime pt;
+    PointArgs pts;
+    int chunk;
+    int kind, padded;
+    const float2* verts;
+    const float4* rects;
+    float* part;
+};
+
+// One work item: pose tile [g0, g0 + blockDim) of SceneDmin sd, point chunk c.
+struct DminItem {
+    int sd, g0, c, pad;
+};
+
+// Register class of a footprint bucket in the persistent kernel:
+// 0 polygons up to 16 padded vertices, 1 larger polygons, 2 rectangle covers.
+constexpr int DMIN_CLASSES = 3;
+inline int dmin_class(int kind, int padded) { return kind == 1 ? 2 : (padded > 16 ? 1 : 0); }
+
+hipError_t launch_batch_reset(int* counters, int n, hipStream_t s);
+hipError_t launch_rollout_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
+                                  int nblk, hipStream_t s);
+hipError_t launch_dmin_persistent(int cls, int block, int grid, const SceneDmin* sds,
+                                  const DminItem* items, int n_items, int* counter, hipStream_t s);
+hipError_t launch_cost_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
+                               int nblk, hipStream_t s);
+hipError_t launch_update_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
+                                 int nblk, hipStream_t s);
+hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
+                                  hipStream_t s);
+hipError_t launch_finalize_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
+                                   hipStream_t s);
+int dmin_persistent_waves(int cls);
+
 }  // namespace emppi

@@ -1,0 +1,224 @@
+// Batched kernels: one control cycle of many independent scenes of uneven
+// size (rollouts, horizon, points, footprint) with a fixed number of launches.
+// Every workgroup runs the same device functions as the single-scene kernels
+// on its scene's arguments, so each scene's results are bit-identical to a
+// single-scene step with the same inputs.
+//
+// The signed-distance stage is one persistent kernel per register class:
+// workgroups pull (scene, pose tile, point chunk) items from a queue ordered
+// longest-first, so scenes of very different cost share the chip without a
+// tail of idle compute units.
+#include "sdf_device.hpp"
+#include "step_device.hpp"
+
+namespace emppi {
+
+namespace {
+
+__global__ void k_batch_reset(int* counters, int n) {
+    if (threadIdx.x < n) counters[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_rollout_b(const SceneStep* __restrict__ steps,
+                                                   const SceneBufs* __restrict__ bufs,
+                                                   const int2* __restrict__ blk) {
+    __shared__ float lds[3 * WAVE * ROLL_HCHUNK];
+    const int2 b = blk[blockIdx.x];  // (scene, first rollout)
+    const SceneStep& S = steps[b.x];
+    const SceneBufs& B = bufs[b.x];
+    RolloutOut o;
+    o.eps_ws = B.eps_ws;
+    o.poses = B.poses;
+    o.jbase = B.jbase;
+    o.diag_poses = nullptr;
+    o.diag_eps = nullptr;
+    o.diag_u = nullptr;
+    rollout_block(S.P, S.U, o, b.y, lds);
+}
+
+// Footprint bucket dispatch.  Class 0: polygons up to 16 padded vertices
+// (register budget for 3 waves per SIMD); class 1: polygons of 20..32
+// padded vertices (2 waves); class 2: rectangle covers (2 waves: up to 32
+// boxes are kept in registers).
+template <int CLS>
+__device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, float4 q, float tau,
+                                              int c0, int c1, float* lds, float& best) {
+    int bi;
+#define EMPPI_POLY(P)                                                                         \
+    case P:                                                                                   \
+        if (moving)                                                                           \
+            dmin_poly_range<P, true, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);   \
+        else                                                                                  \
+            dmin_poly_range<P, false, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);  \
+        return;
+#define EMPPI_RECT(P)                                                                         \
+    case P:                                                                                   \
+        if (moving)                                                                           \
+            dmin_rect_range<P, true, false>(q, tau, S.pts, c0, c1, S.rects, lds, best, bi);   \
+        else                                                                                  \
+            dmin_rect_range<P, false, false>(q, tau, S.pts, c0, c1, S.rects, lds, best, bi);  \
+        return;
+    if (CLS == 0) {
+        switch (S.padded) {
+            EMPPI_POLY(4)
+            EMPPI_POLY(8)
+            EMPPI_POLY(12)
+            EMPPI_POLY(16)
+        default: break;
+        }
+    } else if (CLS == 2) {
+        {
+            switch (S.padded) {
+                EMPPI_RECT(1)
+                EMPPI_RECT(2)
+                EMPPI_RECT(3)
+                EMPPI_RECT(4)
+                EMPPI_RECT(6)
+                EMPPI_RECT(8)
+                EMPPI_RECT(12)
+                EMPPI_RECT(16)
+                EMPPI_RECT(24)
+                EMPPI_RECT(32)
+            default: break;
+            }
+        }
+    } else {
+        switch (S.padded) {
+            EMPPI_POLY(20)
+            EMPPI_POLY(24)
+            EMPPI_POLY(28)
+            EMPPI_POLY(32)
+        default: break;
+        }
+    }
+#undef EMPPI_POLY
+#undef EMPPI_RECT
+    best = INFINITY;  // unreachable for planned items
+}
+
+template <int CLS>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(CLS == 0 ? 3 : 2)))
+void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __restrict__ items,
+                       int n_items, int* __restrict__ counter) {
+    extern __shared__ float lds[];
+    __shared__ int next;
+    for (;;) {
+        __syncthreads();  // the previous item's LDS tile and `next` are no longer read
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        if (it >= n_items) break;
+        const DminItem w = items[it];
+        const SceneDmin& S = sds[w.sd];
+        const int g = w.g0 + static_cast<int>(threadIdx.x);
+        const int npose = S.npose;
+        const bool live = g < npose;
+        const float4 q = live ? S.poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
+        const bool moving = S.pts.vx != nullptr;
+        const float tau = moving ? pose_tau(S.pt, g) : 0.0f;
+        const int nv = *S.pts.n_valid;
+        const int c0 = w.c * S.chunk;
+        const int c1 = min(c0 + S.chunk, nv);
+        float best;
+        dmin_dispatch<CLS>(S, moving, q, tau, c0, c1, lds, best);
+        if (live) S.part[static_cast<size_t>(w.c) * npose + g] = best;
+    }
+}
+
+__global__ __launch_bounds__(COST_THREADS) void k_cost_b(const SceneStep* __restrict__ steps,
+                                                         const SceneBufs* __restrict__ bufs,
+                                                         const int2* __restrict__ blk) {
+    __shared__ float lds[2 * COST_THREADS];
+    const int2 b = blk[blockIdx.x];
+    const SceneBufs& B = bufs[b.x];
+    cost_block(steps[b.x].P, B.part, nullptr, B.nchunk, B.jbase, B.jt, nullptr, nullptr, b.y, lds);
+}
+
+__global__ __launch_bounds__(256) void k_update_b(const SceneStep* __restrict__ steps,
+                                                  const SceneBufs* __restrict__ bufs,
+                                                  const int2* __restrict__ blk) {
+    __shared__ float sh[16];
+    const int2 b = blk[blockIdx.x];  // (scene, horizon step)
+    const SceneStep& S = steps[b.x];
+    const SceneBufs& B = bufs[b.x];
+    update_block(S.P, B.jt, B.eps_ws, S.U, B.unew, nullptr, b.y, sh);
+}
+
+__global__ __launch_bounds__(64) void k_nominal_b(const SceneStep* __restrict__ steps,
+                                                  const SceneBufs* __restrict__ bufs) {
+    __shared__ float lds[3 * MPPI_MAX_T_DEV];
+    const SceneBufs& B = bufs[blockIdx.x];
+    nominal_block(steps[blockIdx.x].P, B.unew, B.nom, lds);
+}
+
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize_b(const SceneStep* __restrict__ steps,
+                                                            const SceneBufs* __restrict__ bufs) {
+    __shared__ float lds[FIN_THREADS];
+    const SceneStep& S = steps[blockIdx.x];
+    const SceneBufs& B = bufs[blockIdx.x];
+    finalize_block(S.P, B.validate, B.part_nom, B.nchunk_nom, B.unew, S.U, B.out4, nullptr, nullptr, lds);
+}
+
+}  // namespace
+
+int dmin_persistent_waves(int cls) { return cls == 0 ? 3 : 2; }
+
+hipError_t launch_batch_reset(int* counters, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollout_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
+                                  int nblk, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rollout_b, dim3(nblk), dim3(256), 0, s, steps, bufs, blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_dmin_persistent(int cls, int block, int grid, const SceneDmin* sds,
+                                  const DminItem* items, int n_items, int* counter, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    // LDS tile sized for moving points (16 bytes per point)
+    const size_t lds = static_cast<size_t>(DMIN_TILE) * 16;
+    if (cls == 0)
+        hipLaunchKernelGGL(k_dmin_persistent<0>, dim3(grid), dim3(block), lds, s, sds, items,
+                           n_items, counter);
+    else if (cls == 1)
+        hipLaunchKernelGGL(k_dmin_persistent<1>, dim3(grid), dim3(block), lds, s, sds, items,
+                           n_items, counter);
+    else
+        hipLaunchKernelGGL(k_dmin_persistent<2>, dim3(grid), dim3(block), lds, s, sds, items,
+                           n_items, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
+                               int nblk, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cost_b, dim3(nblk), dim3(COST_THREADS), 0, s, steps, bufs, blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
+                                 int nblk, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_b, dim3(nblk), dim3(256), 0, s, steps, bufs, blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
+                                  hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nominal_b, dim3(n), dim3(WAVE), 0, s, steps, bufs);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
+                                   hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_b, dim3(n), dim3(FIN_THREADS), 0, s, steps, bufs);
+    return hipGetLastError();
+}
+
+}  // namespace emppi
