@@ -216,6 +216,13 @@ MPPI_API int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, fl
 MPPI_API int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block,
                            int* out_nchunk);
 
+/* The autotuned tile table of a context as text, one line per shape:
+ * "kind padded moving npose n block nchunk".  mppi_tune_get writes it to buf
+ * (host, len bytes; error MPPI_E_CAPACITY if it does not fit), mppi_tune_set
+ * adds the lines of text (host, NUL-terminated) to the context's table.     */
+MPPI_API int mppi_tune_get(mppi_ctx ctx, char* buf, int len);
+MPPI_API int mppi_tune_set(mppi_ctx ctx, const char* text);
+
 /* Fix the tile shape of every fused signed-distance launch of this context
  * (block = poses per workgroup: 64, 128 or 256; nchunk = point chunks, >= 1);
  * block = 0 returns to the autotuned / default shapes.  Results are
@@ -286,6 +293,64 @@ MPPI_API int mppi_batch_autotune(mppi_batch b, int reps, double* out_work_per_it
  * NULL.                                                                     */
 MPPI_API int mppi_batch_info(mppi_batch b, long long* items_main, long long* items_validation,
                              double* work_per_item);
+
+/* ------------------------------------------------------------------------
+ * Learned sampling proposal (not part of the paper's method, which is
+ * training-free): a multilayer perceptron maps features of the current state
+ * to the mean control sequence MPPI samples around.  Features (in_dim =
+ * 64 + 2 + T*nu floats): 64 polar bins of the minimum range of the valid
+ * obstacle points in the robot frame (bins of a pseudo-angle, 16 per
+ * quadrant; range clipped at r_max, divided by r_max; empty bin = 1), the
+ * goal in the robot frame divided by r_max, and the previous control
+ * sequence scaled to [-1, 1] by the control box.  Network: in_dim -> hidden
+ * -> hidden -> T*nu, exact-erf GELU, bf16 operands on the matrix cores with
+ * fp32 accumulation, fp32 master weights.  Outputs are in the same [-1, 1]
+ * control scaling.  Training: mean squared error, Adam (0.9, 0.999, 1e-8).
+ * Parameter vector (fp32): W1[in][hidden], b1, W2[hidden][hidden], b2,
+ * W3[hidden][T*nu], b3.  All calls are stream-ordered on the proposal's
+ * stream unless stated otherwise.
+ * ------------------------------------------------------------------------ */
+typedef struct mppi_proposal_s* mppi_proposal;
+
+/* Shape: horizon T, control width nu, hidden width, largest batch.  Weights
+ * start at zero (set them with proposal_set_params or proposal_load).      */
+MPPI_API int proposal_create(mppi_proposal* out, int device, void* hip_stream, int T, int nu,
+                             int hidden, int max_batch);
+MPPI_API int proposal_destroy(mppi_proposal p);
+MPPI_API const char* proposal_last_error(mppi_proposal p);
+MPPI_API long long proposal_num_params(mppi_proposal p);
+MPPI_API int proposal_shape(mppi_proposal p, int* in_dim, int* hidden, int* out_dim);
+/* Copy the flat fp32 parameter vector in / out (host, n = num_params);
+ * set_params also resets the Adam state.  Synchronous.                     */
+MPPI_API int proposal_set_params(mppi_proposal p, const float* host, long long n);
+MPPI_API int proposal_get_params(mppi_proposal p, float* host, long long n);
+/* Goal (prm->goal), control box (prm->u_min, u_max) and range clip used by
+ * features, outputs and target normalisation.                              */
+MPPI_API int proposal_set_scaling(mppi_proposal p, const mppi_params* prm, float r_max);
+/* Features of M states (dq0: device M x 3 poses; dU_prev: device M x T x nu)
+ * against the valid points of ctx, into dfeat (device M x in_dim).          */
+MPPI_API int proposal_features(mppi_proposal p, mppi_ctx ctx, const float* dq0,
+                               const float* dU_prev, int M, float* dfeat);
+/* Network output (scaled units, device M x T*nu) of M feature rows.        */
+MPPI_API int proposal_forward(mppi_proposal p, const float* dfeat, int M, float* dout);
+/* Sampling mean: the output mapped back into the control box (device
+ * M x T x nu), ready to be the nominal of mppi_step.                        */
+MPPI_API int proposal_mean(mppi_proposal p, const float* dfeat, int M, float* dU);
+/* Control sequences (device M x T x nu) -> scaled training targets.         */
+MPPI_API int proposal_normalize(mppi_proposal p, const float* dU, int M, float* dtarget);
+/* One Adam step on the mean squared error of M rows (dfeat, dtarget device;
+ * targets in scaled units).  loss_out (host, may be NULL) receives the loss
+ * of the forward pass before the update (synchronous when given).          */
+MPPI_API int proposal_train_step(mppi_proposal p, const float* dfeat, const float* dtarget, int M,
+                                 float lr, float* loss_out);
+/* Copy an intermediate of the last forward / training pass to the host (for
+ * gradient checks): 0 pre-activation 1, 1 pre-activation 2, 2 output, 3 dOut,
+ * 4 dH2, 5 dH1, 6 gradient vector (parameter layout); bf16 buffers widened to
+ * float: 10 input, 11 activation 1, 12 activation 2, 13 dOut, 14 dH2, 15 dH1. */
+MPPI_API int proposal_get_buffer(mppi_proposal p, int which, float* host, long long n);
+/* Flat binary file: header, Adam step, scaling, parameters, Adam moments.   */
+MPPI_API int proposal_save(mppi_proposal p, const char* path);
+MPPI_API int proposal_load(mppi_proposal p, const char* path);
 
 #ifdef __cplusplus
 }

@@ -553,3 +553,58 @@ EXPORT int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Features of the learned proposal in the FP32 sequence (not part of the   */
+/* paper's method).  Every operation is one correctly rounded binary32      */
+/* operation, so the result is reproducible bit for bit:                    */
+/*   robot frame: (s, c) = sincos(theta0); d = o - q0; x = c dx + s dy,     */
+/*     y = c dy - s dx;                                                     */
+/*   bin: quadrant q and pseudo-angle t in [0, 1] (y/(x+y), -x/(y-x),       */
+/*     -y/(-x-y), x/(x-y) for q = 0..3; the origin has t = 0),              */
+/*     bin = 16 q + min(15, floor(16 t));                                   */
+/*   value: min over the bin of min(sqrt(x x + y y), r_max), / r_max;       */
+/*     empty bins are r_max / r_max = 1;                                    */
+/*   goal (g - q0) rotated the same way, / r_max;                           */
+/*   previous controls (u - mid) / half per channel (0 when half = 0).      */
+/* ======================================================================== */
+EXPORT void orc_f32_features(const float* px, const float* py, const unsigned char* valid, long n,
+                             const float q0[3], const float goal[2], const float* U_prev, int T,
+                             int nu, const float* umin, const float* umax, float r_max, float* out) {
+    float hist[64];
+    for (int b = 0; b < 64; ++b) hist[b] = r_max;
+    float s, c;
+    orc_f32_sincos(q0[2], &s, &c);
+    for (long i = 0; i < n; ++i) {
+        if (valid && !valid[i]) continue;
+        if (!isfinite(px[i]) || !isfinite(py[i])) continue;
+        float dx = px[i] - q0[0], dy = py[i] - q0[1];
+        float x = c * dx + s * dy;
+        float y = c * dy - s * dx;
+        int q;
+        float t;
+        if (y >= 0.0f) {
+            if (x >= 0.0f) { q = 0; t = (x == 0.0f && y == 0.0f) ? 0.0f : y / (x + y); }
+            else { q = 1; t = -x / (y - x); }
+        } else {
+            if (x < 0.0f) { q = 2; t = -y / (-x - y); }
+            else { q = 3; t = x / (x - y); }
+        }
+        int k = (int)(t * 16.0f);
+        if (k > 15) k = 15;
+        int bin = q * 16 + k;
+        float r = sqrtf(x * x + y * y);
+        if (r > r_max) r = r_max;
+        if (r < hist[bin]) hist[bin] = r;
+    }
+    for (int b = 0; b < 64; ++b) out[b] = hist[b] / r_max;
+    float gx = goal[0] - q0[0], gy = goal[1] - q0[1];
+    out[64] = (c * gx + s * gy) / r_max;
+    out[65] = (c * gy - s * gx) / r_max;
+    for (int k = 0; k < T * nu; ++k) {
+        int ch = k % nu;
+        float mid = (umax[ch] + umin[ch]) * 0.5f;
+        float half = (umax[ch] - umin[ch]) * 0.5f;
+        out[66 + k] = half > 0.0f ? (U_prev[k] - mid) / half : 0.0f;
+    }
+}

@@ -84,6 +84,7 @@ def lib():
                                       vp, vp, vp]
         L.orc_rollout_nominal_f32.argtypes = [i, i, i, f, f, vp, vp, i, vp]
         L.orc_num_threads.restype = i
+        L.orc_f32_features.argtypes = [vp, vp, vp, l, vp, vp, vp, i, i, vp, vp, f, vp]
         _lib = L
     return _lib
 
@@ -353,4 +354,17 @@ def mppi_step(prm, q0, U, scene, seed, step, stream=0):
         out.update(d_nom=dn, valid=ok, u_star=ustar, U_next=Unext)
     else:
         out.update(valid=True, u_star=Un[0].copy(), U_next=np.concatenate([Un[1:], Un[-1:]]))
+    return out
+
+
+def f32_features(ox, oy, valid, q0, goal, U_prev, u_min, u_max, r_max=8.0):
+    """Proposal features of one state in the FP32 sequence (64 + 2 + T*nu floats)."""
+    ox, oy = _f32(ox), _f32(oy)
+    U_prev = _f32(U_prev)
+    T, nu = U_prev.shape
+    valid = None if valid is None else np.ascontiguousarray(valid, dtype=np.uint8)
+    out = np.empty(66 + T * nu, dtype=np.float32)
+    lib().orc_f32_features(_p(ox), _p(oy), _p(valid), ox.size, _p(_f32(q0)), _p(_f32(goal)),
+                           _p(U_prev), T, nu, _p(_vec3(u_min, -1.0)), _p(_vec3(u_max, 1.0)),
+                           np.float32(r_max), _p(out))
     return out

@@ -27,10 +27,15 @@ MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
            "set_footprint", "set_points",
            "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
-           "mppi_autotune", "mppi_set_tiles", "mppi_set_profiling", "mppi_get_profile",
+           "mppi_autotune", "mppi_tune_get", "mppi_tune_set", "mppi_set_tiles",
+           "mppi_set_profiling", "mppi_get_profile",
            "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
            "mppi_batch_u_offsets", "mppi_batch_refresh", "mppi_step_batched",
-           "mppi_batch_autotune", "mppi_batch_info")
+           "mppi_batch_autotune", "mppi_batch_info",
+           "proposal_create", "proposal_destroy", "proposal_last_error", "proposal_num_params",
+           "proposal_shape", "proposal_set_params", "proposal_get_params", "proposal_set_scaling",
+           "proposal_features", "proposal_forward", "proposal_mean", "proposal_normalize",
+           "proposal_train_step", "proposal_get_buffer", "proposal_save", "proposal_load")
 
 
 class MppiError(RuntimeError):
@@ -85,6 +90,8 @@ def load():
     L.mppi_autotune.argtypes = [vp, ctypes.POINTER(MppiParams), i, ctypes.POINTER(i),
                                 ctypes.POINTER(i)]
     L.mppi_set_tiles.argtypes = [vp, i, i]
+    L.mppi_tune_get.argtypes = [vp, ctypes.c_char_p, i]
+    L.mppi_tune_set.argtypes = [vp, ctypes.c_char_p]
     L.mppi_set_profiling.argtypes = [vp, i]
     L.mppi_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_longlong)]
@@ -99,8 +106,29 @@ def load():
     L.mppi_batch_autotune.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
     L.mppi_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
+    ll = ctypes.c_longlong
+    L.proposal_create.argtypes = [ctypes.POINTER(vp), i, vp, i, i, i, i]
+    L.proposal_destroy.argtypes = [vp]
+    L.proposal_last_error.argtypes = [vp]
+    L.proposal_last_error.restype = ctypes.c_char_p
+    L.proposal_num_params.argtypes = [vp]
+    L.proposal_num_params.restype = ll
+    L.proposal_shape.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.proposal_set_params.argtypes = [vp, vp, ll]
+    L.proposal_get_params.argtypes = [vp, vp, ll]
+    L.proposal_set_scaling.argtypes = [vp, ctypes.POINTER(MppiParams), f]
+    L.proposal_features.argtypes = [vp, vp, vp, vp, i, vp]
+    L.proposal_forward.argtypes = [vp, vp, i, vp]
+    L.proposal_mean.argtypes = [vp, vp, i, vp]
+    L.proposal_normalize.argtypes = [vp, vp, i, vp]
+    L.proposal_train_step.argtypes = [vp, vp, vp, i, f, ctypes.POINTER(f)]
+    L.proposal_get_buffer.argtypes = [vp, i, vp, ll]
+    L.proposal_save.argtypes = [vp, ctypes.c_char_p]
+    L.proposal_load.argtypes = [vp, ctypes.c_char_p]
     for name in EXPORTS:
-        if name not in ("mppi_last_error", "mppi_batch_last_error"):
+        if name in ("proposal_num_params",):
+            continue
+        if name not in ("mppi_last_error", "mppi_batch_last_error", "proposal_last_error"):
             getattr(L, name).restype = i
     _lib = L
     return L
@@ -244,6 +272,14 @@ class Context:
                                            ctypes.byref(c)))
         return b.value, c.value
 
+    def mppi_tune_get(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self.lib.mppi_tune_get(self.h, buf, len(buf)))
+        return buf.value.decode()
+
+    def mppi_tune_set(self, text):
+        self._check(self.lib.mppi_tune_set(self.h, text.encode()))
+
     def mppi_set_tiles(self, block=0, nchunk=0):
         self._check(self.lib.mppi_set_tiles(self.h, int(block), int(nchunk)))
 
@@ -369,3 +405,113 @@ class Batch:
             u_out.ctypes.data_as(vp), valid.ctypes.data_as(vp), int(bool(use_graph))))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return u_out, valid.astype(bool)
+
+
+class Proposal:
+    """Learned sampling proposal (MLP on the matrix cores), see exact_mppi.h."""
+
+    BUFFERS = {"pre1": 0, "pre2": 1, "out": 2, "dout": 3, "dh2": 4, "dh1": 5, "grad": 6,
+               "x": 10, "a1": 11, "a2": 12, "dout_b": 13, "dh2_b": 14, "dh1_b": 15}
+
+    def __init__(self, T, nu, hidden=256, max_batch=1024, device=0, stream=None):
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.proposal_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                      int(T), int(nu), int(hidden), int(max_batch))
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.proposal_last_error(None).decode())
+        self.h = h
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.proposal_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        self.in_dim, self.hidden, self.out_dim = a.value, b.value, c.value
+        self.T, self.nu = int(T), int(nu)
+        self.n_params = int(self.lib.proposal_num_params(self.h))
+
+    def _check(self, rc):
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.proposal_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.proposal_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_params(self, seed):
+        """Glorot-uniform weights and zero biases drawn on the host from `seed`."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        for fi, fo in ((self.in_dim, self.hidden), (self.hidden, self.hidden),
+                       (self.hidden, self.out_dim)):
+            lim = math.sqrt(6.0 / (fi + fo))
+            parts += [rng.uniform(-lim, lim, fi * fo), np.zeros(fo)]
+        theta = np.concatenate(parts).astype(np.float32)
+        self.set_params(theta)
+        return theta
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        self._check(self.lib.proposal_set_params(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+
+    def get_params(self):
+        a = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.proposal_get_params(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+        return a
+
+    def set_scaling(self, prm, r_max=8.0):
+        p = make_params(prm)
+        self._check(self.lib.proposal_set_scaling(self.h, ctypes.byref(p), float(r_max)))
+
+    def features(self, ctx, q0, U_prev):
+        q0 = _dev_f32(q0, self.device, "q0").reshape(-1, 3).contiguous()
+        U_prev = _dev_f32(U_prev, self.device, "U_prev").contiguous()
+        M = q0.shape[0]
+        out = torch.empty((M, self.in_dim), dtype=torch.float32, device=self.device)
+        self._check(self.lib.proposal_features(self.h, ctx.h, _ptr(q0), _ptr(U_prev), M, _ptr(out)))
+        return out
+
+    def forward(self, feat):
+        feat = _dev_f32(feat, self.device, "feat")
+        out = torch.empty((feat.shape[0], self.out_dim), dtype=torch.float32, device=self.device)
+        self._check(self.lib.proposal_forward(self.h, _ptr(feat), feat.shape[0], _ptr(out)))
+        return out
+
+    def mean(self, feat):
+        feat = _dev_f32(feat, self.device, "feat")
+        U = torch.empty((feat.shape[0], self.T, self.nu), dtype=torch.float32, device=self.device)
+        self._check(self.lib.proposal_mean(self.h, _ptr(feat), feat.shape[0], _ptr(U)))
+        return U
+
+    def normalize(self, U):
+        U = _dev_f32(U, self.device, "U")
+        M = U.numel() // (self.T * self.nu)
+        y = torch.empty((M, self.out_dim), dtype=torch.float32, device=self.device)
+        self._check(self.lib.proposal_normalize(self.h, _ptr(U), M, _ptr(y)))
+        return y
+
+    def train_step(self, feat, target, lr, want_loss=True):
+        feat = _dev_f32(feat, self.device, "feat")
+        target = _dev_f32(target, self.device, "target")
+        loss = ctypes.c_float()
+        self._check(self.lib.proposal_train_step(self.h, _ptr(feat), _ptr(target), feat.shape[0],
+                                                 float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def get_buffer(self, name, n):
+        a = np.empty(int(n), dtype=np.float32)
+        self._check(self.lib.proposal_get_buffer(self.h, self.BUFFERS[name],
+                                                 a.ctypes.data_as(ctypes.c_void_p), a.size))
+        return a
+
+    def save(self, path):
+        self._check(self.lib.proposal_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(self.lib.proposal_load(self.h, str(path).encode()))

@@ -10,8 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libexact_mppi.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["capi.hip", "capi_batch.hip", "kernels_sdf.hip", "kernels_step.hip",
-           "kernels_batch.hip"]
+SOURCES = ["capi.hip", "capi_batch.hip", "capi_mlp.hip", "kernels_sdf.hip", "kernels_step.hip",
+           "kernels_batch.hip", "kernels_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

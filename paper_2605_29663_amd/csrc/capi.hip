@@ -21,7 +21,7 @@ using namespace emppi;
 using namespace emppi_host;
 
 static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
-                           float* deps, float* du);
+                           float* deps, float* du, bool argmin);
 
 extern "C" {
 
@@ -57,8 +57,8 @@ int mppi_destroy(mppi_ctx ctx) {
         DevBuf* bufs[] = {&ctx->poly_verts, &ctx->poly_tab_a, &ctx->poly_tab_b, &ctx->rects,
                           &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
                           &ctx->eps_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
-                          &ctx->part, &ctx->part_idx, &ctx->unew, &ctx->nom_poses,
-                          &ctx->part_nom, &ctx->out4};
+                          &ctx->key, &ctx->key64, &ctx->unew, &ctx->nom_poses,
+                          &ctx->key_nom, &ctx->out4};
         for (DevBuf* b : bufs) b->release();
         if (ctx->h_out) (void)hipHostFree(ctx->h_out);
         if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -230,25 +230,39 @@ int sdf_min_poses(mppi_ctx ctx, const float* dposes, int K, int T, float dt, int
     if (np == 0) return MPPI_OK;
     DeviceGuard g(ctx->device);
     PoseTime pt{1, T, state_offset ? 1 : 0, dt};
-    int nchunk = 1;
-    if (int rc = run_dmin(ctx, reinterpret_cast<const float4*>(dposes), static_cast<int>(np), pt,
-                          kind, dargmin != nullptr, ctx->part, &ctx->part_idx, nchunk))
+    unsigned int* key = nullptr;
+    unsigned long long* key64 = nullptr;
+    if (dargmin) {
+        HIP_TRY(ctx, ctx->key64.ensure(sizeof(unsigned long long) * np));
+        key64 = ctx->key64.as<unsigned long long>();
+    } else {
+        HIP_TRY(ctx, ctx->key.ensure(sizeof(unsigned int) * np));
+        key = ctx->key.as<unsigned int>();
+    }
+    HIP_TRY(ctx, launch_key_init(key, key64, static_cast<int>(np), ctx->stream));
+    if (int rc = run_dmin(ctx, reinterpret_cast<const float4*>(dposes), static_cast<int>(np), pt, kind,
+                          key, key64))
         return rc;
-    HIP_TRY(ctx, launch_dmin_finalize(ctx->part.as<float>(), dargmin ? ctx->part_idx.as<int>() : nullptr,
-                                      nchunk, static_cast<int>(np), dd_min, dargmin, ctx->stream));
+    HIP_TRY(ctx, launch_dmin_finalize(key, key64, static_cast<int>(np), dd_min, dargmin, ctx->stream));
     return MPPI_OK;
 }
 
 static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
-                           float* deps, float* du) {
+                           float* deps, float* du, bool argmin) {
     const size_t Kpad = A.Kpad, T = A.T, nu = A.nu;
     HIP_TRY(ctx, ctx->eps_ws.ensure(sizeof(float) * T * nu * Kpad));
     HIP_TRY(ctx, ctx->poses_ws.ensure(sizeof(float4) * T * Kpad));
     HIP_TRY(ctx, ctx->jbase.ensure(sizeof(float) * Kpad));
+    if (argmin)
+        HIP_TRY(ctx, ctx->key64.ensure(sizeof(unsigned long long) * T * Kpad));
+    else
+        HIP_TRY(ctx, ctx->key.ensure(sizeof(unsigned int) * T * Kpad));
     RolloutOut o;
     o.eps_ws = ctx->eps_ws.as<float>();
     o.poses = ctx->poses_ws.as<float4>();
     o.jbase = ctx->jbase.as<float>();
+    o.key = argmin ? nullptr : ctx->key.as<unsigned int>();
+    o.key64 = argmin ? ctx->key64.as<unsigned long long>() : nullptr;
     o.diag_poses = dposes;
     o.diag_eps = deps;
     o.diag_u = du;
@@ -265,7 +279,7 @@ int mppi_rollout(mppi_ctx ctx, const mppi_params* prm, const float* q0, const fl
     if (!valid_model(prm->model, prm->nu)) return fail(ctx, MPPI_E_ARG, "model/nu mismatch");
     DeviceGuard g(ctx->device);
     const StepArgs A = make_args(prm, q0, seed, step);
-    return rollout_into_ws(ctx, A, dU, dposes, deps, du);
+    return rollout_into_ws(ctx, A, dU, dposes, deps, du, false);
 }
 
 int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, uint64_t seed,
@@ -279,19 +293,20 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
     const int kind = prm->footprint_kind;
     const size_t Kpad = A.Kpad, T = A.T, nu = A.nu;
 
-    // 1. sampling + rollouts
-    if (int rc = rollout_into_ws(ctx, A, dU, D.poses, D.eps, D.u)) return rc;
+    // 1. sampling + rollouts (also initialises the distance keys)
+    const bool argmin = D.argmin != nullptr;
+    if (int rc = rollout_into_ws(ctx, A, dU, D.poses, D.eps, D.u, argmin)) return rc;
+    unsigned int* key = argmin ? nullptr : ctx->key.as<unsigned int>();
+    unsigned long long* key64 = argmin ? ctx->key64.as<unsigned long long>() : nullptr;
     // 2. signed distances, min over points
-    int nchunk = 1;
     PoseTime pt{A.Kpad, A.T, A.state_offset, A.dt};
     if (ctx->prof) HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    if (int rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), static_cast<int>(T * Kpad), pt, kind,
-                          D.argmin != nullptr, ctx->part, &ctx->part_idx, nchunk))
+    if (int rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), static_cast<int>(T * Kpad), pt, kind, key,
+                          key64))
         return rc;
     if (ctx->prof) HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIP_TRY(ctx, ctx->jt.ensure(sizeof(float) * Kpad));
-    HIP_TRY(ctx, launch_cost(A, ctx->part.as<float>(), D.argmin ? ctx->part_idx.as<int>() : nullptr,
-                             nchunk, ctx->jbase.as<float>(), ctx->jt.as<float>(), D.d_min,
+    HIP_TRY(ctx, launch_cost(A, key, key64, ctx->jbase.as<float>(), ctx->jt.as<float>(), D.d_min,
                              D.argmin, ctx->stream));
     if (D.J)
         HIP_TRY(ctx, hipMemcpyAsync(D.J, ctx->jt.p, sizeof(float) * A.K, hipMemcpyDeviceToDevice, ctx->stream));
@@ -300,16 +315,17 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
     HIP_TRY(ctx, launch_update(A, ctx->jt.as<float>(), ctx->eps_ws.as<float>(), dU,
                                ctx->unew.as<float>(), D.w, ctx->stream));
     // 4. validation
-    int nchunk_nom = 1;
+    HIP_TRY(ctx, ctx->key_nom.ensure(sizeof(unsigned int) * T));
     if (prm->validate) {
         HIP_TRY(ctx, ctx->nom_poses.ensure(sizeof(float4) * T));
-        HIP_TRY(ctx, launch_nominal(A, ctx->unew.as<float>(), ctx->nom_poses.as<float4>(), ctx->stream));
+        HIP_TRY(ctx, launch_nominal(A, ctx->unew.as<float>(), ctx->nom_poses.as<float4>(),
+                                    ctx->key_nom.as<unsigned int>(), ctx->stream));
         PoseTime ptn{1, A.T, A.state_offset, A.dt};
-        if (int rc = run_dmin(ctx, ctx->nom_poses.as<float4>(), A.T, ptn, kind, false,
-                              ctx->part_nom, nullptr, nchunk_nom))
+        if (int rc = run_dmin(ctx, ctx->nom_poses.as<float4>(), A.T, ptn, kind,
+                              ctx->key_nom.as<unsigned int>(), nullptr))
             return rc;
     }
-    HIP_TRY(ctx, launch_finalize(A, prm->validate ? 1 : 0, ctx->part_nom.as<float>(), nchunk_nom,
+    HIP_TRY(ctx, launch_finalize(A, prm->validate ? 1 : 0, ctx->key_nom.as<unsigned int>(),
                                  ctx->unew.as<float>(), dU, ctx->out4.as<float>(), D.U_upd,
                                  D.d_nom, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_out, ctx->out4.p, 4 * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
@@ -335,7 +351,7 @@ int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block
     // poses of one sampled step around a zero nominal
     HIP_TRY(ctx, ctx->unew.ensure(sizeof(float) * A.T * A.nu));
     HIP_TRY(ctx, hipMemsetAsync(ctx->unew.p, 0, sizeof(float) * A.T * A.nu, ctx->stream));
-    if (int rc = rollout_into_ws(ctx, A, ctx->unew.as<float>(), nullptr, nullptr, nullptr)) return rc;
+    if (int rc = rollout_into_ws(ctx, A, ctx->unew.as<float>(), nullptr, nullptr, nullptr, false)) return rc;
     const int kind = prm->footprint_kind;
     const int padded = kind == 0 ? ctx->BP : ctx->RP;
     const int npose = A.T * A.Kpad;
@@ -351,13 +367,13 @@ int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block
     for (int b : blocks) {
         for (int nc : chunk_counts) {
             if (nc > 1 && ctx->n_points / nc < 32) continue;
-            int nchunk = 1;
+            unsigned int* key = ctx->key.as<unsigned int>();
             // one untimed launch, then reps timed ones
-            rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), npose, pt, kind, false, ctx->part, nullptr, nchunk, b, nc);
+            rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), npose, pt, kind, key, nullptr, b, nc);
             if (rc) break;
             hipError_t e = hipEventRecord(e0, ctx->stream);
             for (int k = 0; k < reps && rc == MPPI_OK; ++k)
-                rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), npose, pt, kind, false, ctx->part, nullptr, nchunk, b, nc);
+                rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), npose, pt, kind, key, nullptr, b, nc);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -381,6 +397,39 @@ int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block
     ctx->tuned[std::make_tuple(kind, padded, ctx->moving ? 1 : 0, npose, ctx->n_points)] = {best_b, best_c};
     if (out_block) *out_block = best_b;
     if (out_nchunk) *out_nchunk = best_c;
+    return MPPI_OK;
+}
+
+int mppi_tune_get(mppi_ctx ctx, char* buf, int len) {
+    if (!ctx || !buf || len < 1) return MPPI_E_ARG;
+    std::string text;
+    char line[160];
+    for (const auto& kv : ctx->tuned) {
+        std::snprintf(line, sizeof line, "%d %d %d %d %d %d %d\n", std::get<0>(kv.first),
+                      std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                      std::get<4>(kv.first), kv.second.first, kv.second.second);
+        text += line;
+    }
+    if (static_cast<int>(text.size()) + 1 > len) return fail(ctx, MPPI_E_CAPACITY, "buffer too small");
+    std::memcpy(buf, text.c_str(), text.size() + 1);
+    return MPPI_OK;
+}
+
+int mppi_tune_set(mppi_ctx ctx, const char* text) {
+    if (!ctx || !text) return MPPI_E_ARG;
+    const char* p = text;
+    while (*p) {
+        int v[7];
+        int used = 0;
+        if (std::sscanf(p, "%d %d %d %d %d %d %d%n", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                        &used) != 7)
+            break;
+        if ((v[5] != 64 && v[5] != 128 && v[5] != 256) || v[6] < 1)
+            return fail(ctx, MPPI_E_ARG, "bad tile line");
+        ctx->tuned[std::make_tuple(v[0], v[1], v[2], v[3], v[4])] = {v[5], v[6]};
+        p += used;
+        while (*p == '\n' || *p == ' ' || *p == '\r') ++p;
+    }
     return MPPI_OK;
 }
 

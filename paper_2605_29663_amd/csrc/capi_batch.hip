@@ -133,8 +133,8 @@ int plan(mppi_batch b, double work_per_item) {
         chunk_nom[s] = std::max(1, (npts + nchunk_nom[s] - 1) / nchunk_nom[s]);
         const size_t sizes[9] = {sizeof(float) * T * nu * Kpad, sizeof(float4) * T * Kpad,
                                  sizeof(float) * Kpad, sizeof(float) * Kpad,
-                                 sizeof(float) * nchunk[s] * T * Kpad, sizeof(float) * T * nu,
-                                 sizeof(float4) * T, sizeof(float) * nchunk_nom[s] * T, 0};
+                                 sizeof(unsigned int) * T * Kpad, sizeof(float) * T * nu,
+                                 sizeof(float4) * T, sizeof(unsigned int) * T, 0};
         for (int k = 0; k < 9; ++k) {
             off[s * 9 + k] = total;
             total += align256(sizes[k]);
@@ -154,12 +154,10 @@ int plan(mppi_batch b, double work_per_item) {
         B.poses = reinterpret_cast<float4*>(base + off[s * 9 + 1]);
         B.jbase = reinterpret_cast<float*>(base + off[s * 9 + 2]);
         B.jt = reinterpret_cast<float*>(base + off[s * 9 + 3]);
-        B.part = reinterpret_cast<float*>(base + off[s * 9 + 4]);
-        B.nchunk = nchunk[s];
+        B.key = reinterpret_cast<unsigned int*>(base + off[s * 9 + 4]);
         B.unew = reinterpret_cast<float*>(base + off[s * 9 + 5]);
         B.nom = reinterpret_cast<float4*>(base + off[s * 9 + 6]);
-        B.part_nom = reinterpret_cast<float*>(base + off[s * 9 + 7]);
-        B.nchunk_nom = nchunk_nom[s];
+        B.key_nom = reinterpret_cast<unsigned int*>(base + off[s * 9 + 7]);
         B.out4 = b->d_out.as<float>() + 4 * s;
         B.validate = P.validate ? 1 : 0;
         const int cls = dmin_class(kind, padded);
@@ -175,7 +173,7 @@ int plan(mppi_batch b, double work_per_item) {
             D.padded = padded;
             D.verts = c->poly_verts.as<float2>();
             D.rects = c->rects.as<float4>();
-            D.part = pass == 0 ? B.part : B.part_nom;
+            D.key = pass == 0 ? B.key : B.key_nom;
             if (pass == 1 && !P.validate) continue;
             const int tile = pass == 0 ? 256 : 128;
             const int nck = pass == 0 ? nchunk[s] : nchunk_nom[s];

@@ -72,7 +72,7 @@ struct mppi_ctx_s {
     bool moving = false;
     DevBuf px, py, pvx, pvy, pidx, n_valid;
     // step workspaces
-    DevBuf eps_ws, poses_ws, jbase, jt, part, part_idx, unew, nom_poses, part_nom, out4;
+    DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom, out4;
     float* h_out = nullptr;  // pinned
     // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
     std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
@@ -288,9 +288,11 @@ inline void choose_tiles(int kind, int padded, int npose, int n_points, int& blo
     nchunk = std::max(1, (n_points + chunk - 1) / chunk);
 }
 
-inline int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind, bool argmin,
-             DevBuf& part, DevBuf* part_idx, int& nchunk_out, int force_block = 0,
-             int force_nchunk = 0) {
+// Fused transform + signed distance + min launch; the keys (key, or key64
+// when argmin) must hold their initial values for the poses.
+inline int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind,
+                    unsigned int* key, unsigned long long* key64, int force_block = 0,
+                    int force_nchunk = 0) {
     const int padded = kind == 0 ? ctx->BP : ctx->RP;
     int block, nchunk, chunk;
     choose_tiles(kind, padded, npose, ctx->n_points, block, nchunk, chunk);
@@ -307,8 +309,6 @@ inline int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, i
     if (force_nchunk) nchunk = force_nchunk;
     chunk = std::max(1, (ctx->n_points + nchunk - 1) / nchunk);
     nchunk = std::max(1, (ctx->n_points + chunk - 1) / chunk);
-    HIP_TRY(ctx, part.ensure(sizeof(float) * static_cast<size_t>(npose) * nchunk));
-    if (argmin) HIP_TRY(ctx, part_idx->ensure(sizeof(int) * static_cast<size_t>(npose) * nchunk));
     DminLaunch L{};
     L.poses = poses;
     L.npose = npose;
@@ -321,11 +321,10 @@ inline int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, i
     L.verts = ctx->poly_verts.as<float2>();
     L.rects = ctx->rects.as<float4>();
     L.padded = padded;
-    L.argmin = argmin;
-    L.part = part.as<float>();
-    L.part_idx = argmin ? part_idx->as<int>() : nullptr;
+    L.argmin = key64 != nullptr;
+    L.key = key;
+    L.key64 = key64;
     HIP_TRY(ctx, launch_dmin(L, ctx->stream));
-    nchunk_out = nchunk;
     return MPPI_OK;
 }
 

@@ -36,9 +36,25 @@ struct PoseTime {
     float dt;
 };
 
+// Order-preserving keys of the signed squared distance s: the unsigned order
+// of key(s) is the order of s (sign bit flipped for s >= 0, all bits for
+// s < 0).  Chunks of points merge their minima with atomicMin on these keys
+// (exact and order-independent, hence deterministic); with the argmin, the
+// 64-bit key is key(s) << 32 | point index, so ties go to the lowest index.
+constexpr unsigned int DKEY_INIT = 0xFF800000u;                 // key(+inf)
+constexpr unsigned long long DKEY64_INIT = 0xFF800000FFFFFFFFull;  // (+inf, index -1)
+
+__device__ __forceinline__ unsigned int dkey(float s) {
+    const unsigned int u = __float_as_uint(s);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float dkey_value(unsigned int k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
 // One launch of the fused transform + signed distance + min-over-points
 // stage: npose poses, points split into nchunk chunks of `chunk` points;
-// partial minima of the signed squared distance go to part[c * npose + g].
+// each (pose, chunk) minimum is merged into key[g] (or key64[g]).
 struct DminLaunch {
     const float4* poses;
     int npose;
@@ -50,14 +66,15 @@ struct DminLaunch {
     const float4* rects;  // rectangle cover, padded to `padded` boxes (repeats of box 0)
     int padded;
     bool argmin;
-    float* part;
-    int* part_idx;
+    unsigned int* key;         // [npose], initialised to DKEY_INIT
+    unsigned long long* key64; // [npose], initialised to DKEY64_INIT (argmin)
 };
 
 hipError_t launch_dmin(const DminLaunch& L, hipStream_t s);
 int dmin_padded_count(int kind, int count);  // bucket a footprint size is padded to
 
-hipError_t launch_dmin_finalize(const float* part, const int* part_idx, int nchunk, int npose,
+hipError_t launch_key_init(unsigned int* key, unsigned long long* key64, int n, hipStream_t s);
+hipError_t launch_dmin_finalize(const unsigned int* key, const unsigned long long* key64, int npose,
                                 float* d_out, int* idx_out, hipStream_t s);
 
 hipError_t launch_sdf_points(int kind, const float* px, const float* py, int n,
@@ -72,6 +89,8 @@ struct RolloutOut {
     float* eps_ws;   // [T][nu][Kpad]
     float4* poses;   // [T][Kpad]
     float* jbase;    // [Kpad]
+    unsigned int* key;          // [T][Kpad] distance keys to initialise (or nullptr)
+    unsigned long long* key64;  // [T][Kpad] (argmin variant, or nullptr)
     float* diag_poses;  // [K][T][4] or nullptr
     float* diag_eps;    // [K][T][nu]
     float* diag_u;      // [K][T][nu]
@@ -79,16 +98,17 @@ struct RolloutOut {
 
 hipError_t launch_rollout(const StepArgs& P, const float* U, const RolloutOut& o, hipStream_t s);
 
-hipError_t launch_cost(const StepArgs& P, const float* part, const int* part_idx, int nchunk,
+hipError_t launch_cost(const StepArgs& P, const unsigned int* key, const unsigned long long* key64,
                        const float* jbase, float* jt, float* diag_dmin, int* diag_argmin,
                        hipStream_t s);
 
 hipError_t launch_update(const StepArgs& P, const float* jt, const float* eps_ws, const float* U,
                          float* Unew, float* diag_w, hipStream_t s);
 
-hipError_t launch_nominal(const StepArgs& P, const float* Unew, float4* nom_poses, hipStream_t s);
+hipError_t launch_nominal(const StepArgs& P, const float* Unew, float4* nom_poses,
+                          unsigned int* key_nom, hipStream_t s);
 
-hipError_t launch_finalize(const StepArgs& P, int validate, const float* part_nom, int nchunk,
+hipError_t launch_finalize(const StepArgs& P, int validate, const unsigned int* key_nom,
                            const float* Unew, float* U, float* out4, float* diag_unew,
                            float* diag_dnom, hipStream_t s);
 
@@ -106,12 +126,10 @@ struct SceneBufs {
     float4* poses;   // [T][Kpad]
     float* jbase;    // [Kpad]
     float* jt;       // [Kpad]
-    float* part;     // [nchunk][T*Kpad]
-    int nchunk;
+    unsigned int* key;      // [T*Kpad] distance keys
     float* unew;     // [T][nu]
     float4* nom;     // [T]
-    float* part_nom; // [nchunk_nom][T]
-    int nchunk_nom;
+    unsigned int* key_nom;  // [T]
     float* out4;     // 4 floats
     int validate;    // run Algorithm 1 step 4 for this scene
 };
@@ -126,7 +144,7 @@ struct SceneDmin {
     int kind, padded;
     const float2* verts;
     const float4* rects;
-    float* part;
+    unsigned int* key;
 };
 
 // One work item: pose tile [g0, g0 + blockDim) of SceneDmin sd, point chunk c.

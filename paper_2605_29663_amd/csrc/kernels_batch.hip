@@ -30,6 +30,8 @@ __global__ __launch_bounds__(256) void k_rollout_b(const SceneStep* __restrict__
     o.eps_ws = B.eps_ws;
     o.poses = B.poses;
     o.jbase = B.jbase;
+    o.key = B.key;
+    o.key64 = nullptr;
     o.diag_poses = nullptr;
     o.diag_eps = nullptr;
     o.diag_u = nullptr;
@@ -122,7 +124,7 @@ void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __rest
         const int c1 = min(c0 + S.chunk, nv);
         float best;
         dmin_dispatch<CLS>(S, moving, q, tau, c0, c1, lds, best);
-        if (live) S.part[static_cast<size_t>(w.c) * npose + g] = best;
+        if (live) atomicMin(&S.key[g], dkey(best));
     }
 }
 
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(COST_THREADS) void k_cost_b(const SceneStep* __rest
     __shared__ float lds[2 * COST_THREADS];
     const int2 b = blk[blockIdx.x];
     const SceneBufs& B = bufs[b.x];
-    cost_block(steps[b.x].P, B.part, nullptr, B.nchunk, B.jbase, B.jt, nullptr, nullptr, b.y, lds);
+    cost_block(steps[b.x].P, B.key, nullptr, B.jbase, B.jt, nullptr, nullptr, b.y, lds);
 }
 
 __global__ __launch_bounds__(256) void k_update_b(const SceneStep* __restrict__ steps,
@@ -149,15 +151,14 @@ __global__ __launch_bounds__(64) void k_nominal_b(const SceneStep* __restrict__ 
                                                   const SceneBufs* __restrict__ bufs) {
     __shared__ float lds[3 * MPPI_MAX_T_DEV];
     const SceneBufs& B = bufs[blockIdx.x];
-    nominal_block(steps[blockIdx.x].P, B.unew, B.nom, lds);
+    nominal_block(steps[blockIdx.x].P, B.unew, B.nom, B.key_nom, lds);
 }
 
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize_b(const SceneStep* __restrict__ steps,
                                                             const SceneBufs* __restrict__ bufs) {
-    __shared__ float lds[FIN_THREADS];
     const SceneStep& S = steps[blockIdx.x];
     const SceneBufs& B = bufs[blockIdx.x];
-    finalize_block(S.P, B.validate, B.part_nom, B.nchunk_nom, B.unew, S.U, B.out4, nullptr, nullptr, lds);
+    finalize_block(S.P, B.validate, B.key_nom, B.unew, S.U, B.out4, nullptr, nullptr);
 }
 
 }  // namespace

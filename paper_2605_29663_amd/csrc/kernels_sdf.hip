@@ -9,7 +9,7 @@ namespace emppi {
 namespace {
 
 // Grid: x over poses (one lane each), y over point chunks of `chunk` points.
-// Partial minima of the signed squared distance go to part[chunk_id][pose].
+// Each chunk's minimum is merged into the pose's key with atomicMin.
 // Waves per SIMD the register budget is tuned for (512 VGPRs per lane).
 template <int BP>
 constexpr int poly_waves() { return BP <= 8 ? 6 : BP <= 16 ? 4 : BP <= 20 ? 3 : 2; }
@@ -19,8 +19,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(poly_waves<
 void k_dmin_poly(const float4* __restrict__ poses, int npose,
                                                    PoseTime pt, PointArgs pts, int chunk,
                                                    const float2* __restrict__ verts,
-                                                   float* __restrict__ part,
-                                                   int* __restrict__ part_idx) {
+                                                   unsigned int* __restrict__ key,
+                                                   unsigned long long* __restrict__ key64) {
     extern __shared__ float lds[];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = g < npose;
@@ -33,9 +33,12 @@ void k_dmin_poly(const float4* __restrict__ poses, int npose,
     int besti;
     dmin_poly_range<BP, MOVING, ARGMIN>(q, tau, pts, c0, c1, verts, lds, best, besti);
     if (live) {
-        const size_t o = static_cast<size_t>(blockIdx.y) * npose + g;
-        part[o] = best;
-        if (ARGMIN) part_idx[o] = besti >= 0 ? pts.idx[besti] : -1;
+        if (ARGMIN) {
+            const unsigned int idx = besti >= 0 ? static_cast<unsigned int>(pts.idx[besti]) : 0xFFFFFFFFu;
+            atomicMin(&key64[g], (static_cast<unsigned long long>(dkey(best)) << 32) | idx);
+        } else {
+            atomicMin(&key[g], dkey(best));
+        }
     }
 }
 
@@ -43,8 +46,8 @@ template <int RP, bool MOVING, bool ARGMIN>
 __global__ __launch_bounds__(256) void k_dmin_rect(const float4* __restrict__ poses, int npose,
                                                    PoseTime pt, PointArgs pts, int chunk,
                                                    const float4* __restrict__ rects,
-                                                   float* __restrict__ part,
-                                                   int* __restrict__ part_idx) {
+                                                   unsigned int* __restrict__ key,
+                                                   unsigned long long* __restrict__ key64) {
     extern __shared__ float lds[];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = g < npose;
@@ -57,30 +60,37 @@ __global__ __launch_bounds__(256) void k_dmin_rect(const float4* __restrict__ po
     int besti;
     dmin_rect_range<RP, MOVING, ARGMIN>(q, tau, pts, c0, c1, rects, lds, best, besti);
     if (live) {
-        const size_t o = static_cast<size_t>(blockIdx.y) * npose + g;
-        part[o] = best;
-        if (ARGMIN) part_idx[o] = besti >= 0 ? pts.idx[besti] : -1;
+        if (ARGMIN) {
+            const unsigned int idx = besti >= 0 ? static_cast<unsigned int>(pts.idx[besti]) : 0xFFFFFFFFu;
+            atomicMin(&key64[g], (static_cast<unsigned long long>(dkey(best)) << 32) | idx);
+        } else {
+            atomicMin(&key[g], dkey(best));
+        }
     }
 }
 
-// Min over chunks (earlier chunk wins ties: lowest point index), then
-// d = sign(s) sqrt(|s|).
-__global__ void k_dmin_finalize(const float* __restrict__ part, const int* __restrict__ part_idx,
-                                int nchunk, int npose, float* __restrict__ d_out,
-                                int* __restrict__ idx_out) {
+__global__ void k_key_init(unsigned int* __restrict__ key, unsigned long long* __restrict__ key64,
+                           int n) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    if (key) key[g] = DKEY_INIT;
+    if (key64) key64[g] = DKEY64_INIT;
+}
+
+// Keys -> d = sign(s) sqrt(|s|) and the argmin index.
+__global__ void k_dmin_finalize(const unsigned int* __restrict__ key,
+                                const unsigned long long* __restrict__ key64, int npose,
+                                float* __restrict__ d_out, int* __restrict__ idx_out) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= npose) return;
-    float s = part[g];
-    int idx = part_idx ? part_idx[g] : -1;
-    for (int c = 1; c < nchunk; ++c) {
-        const float v = part[static_cast<size_t>(c) * npose + g];
-        if (v < s) {
-            s = v;
-            if (part_idx) idx = part_idx[static_cast<size_t>(c) * npose + g];
-        }
+    if (key64) {
+        const unsigned long long k = key64[g];
+        d_out[g] = signed_sqrt(dkey_value(static_cast<unsigned int>(k >> 32)));
+        if (idx_out) idx_out[g] = static_cast<int>(static_cast<unsigned int>(k));
+    } else {
+        d_out[g] = signed_sqrt(dkey_value(key[g]));
+        if (idx_out) idx_out[g] = -1;
     }
-    d_out[g] = signed_sqrt(s);
-    if (idx_out) idx_out[g] = idx;
 }
 
 // ---------------------------------------------------------------- point-wise
@@ -182,14 +192,14 @@ __global__ __launch_bounds__(1024) void k_compact_points(
 template <int BP, bool MOVING, bool ARGMIN>
 hipError_t launch_poly_t(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_dmin_poly<BP, MOVING, ARGMIN>), grid, dim3(L.block), lds, s, L.poses,
-                       L.npose, L.pt, L.pts, L.chunk, L.verts, L.part, L.part_idx);
+                       L.npose, L.pt, L.pts, L.chunk, L.verts, L.key, L.key64);
     return hipGetLastError();
 }
 
 template <int RP, bool MOVING, bool ARGMIN>
 hipError_t launch_rect_t(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_dmin_rect<RP, MOVING, ARGMIN>), grid, dim3(L.block), lds, s, L.poses,
-                       L.npose, L.pt, L.pts, L.chunk, L.rects, L.part, L.part_idx);
+                       L.npose, L.pt, L.pts, L.chunk, L.rects, L.key, L.key64);
     return hipGetLastError();
 }
 
@@ -250,11 +260,17 @@ hipError_t launch_dmin(const DminLaunch& L, hipStream_t s) {
     }
 }
 
-hipError_t launch_dmin_finalize(const float* part, const int* part_idx, int nchunk, int npose,
+hipError_t launch_key_init(unsigned int* key, unsigned long long* key64, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_key_init, dim3((n + 255) / 256), dim3(256), 0, s, key, key64, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dmin_finalize(const unsigned int* key, const unsigned long long* key64, int npose,
                                 float* d_out, int* idx_out, hipStream_t s) {
     if (npose <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dmin_finalize, dim3((npose + 255) / 256), dim3(256), 0, s, part, part_idx,
-                       nchunk, npose, d_out, idx_out);
+    hipLaunchKernelGGL(k_dmin_finalize, dim3((npose + 255) / 256), dim3(256), 0, s, key, key64,
+                       npose, d_out, idx_out);
     return hipGetLastError();
 }
 

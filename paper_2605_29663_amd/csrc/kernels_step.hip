@@ -14,16 +14,15 @@ __global__ __launch_bounds__(256) void k_rollout(StepArgs P, const float* __rest
     rollout_block(P, U, o, blockIdx.x * WAVE, lds);
 }
 
-__global__ __launch_bounds__(COST_THREADS) void k_cost(StepArgs P, const float* __restrict__ part,
-                                                       const int* __restrict__ part_idx,
-                                                       int nchunk,
+__global__ __launch_bounds__(COST_THREADS) void k_cost(StepArgs P,
+                                                       const unsigned int* __restrict__ key,
+                                                       const unsigned long long* __restrict__ key64,
                                                        const float* __restrict__ jbase,
                                                        float* __restrict__ jt,
                                                        float* __restrict__ diag_dmin,
                                                        int* __restrict__ diag_argmin) {
     __shared__ float lds[2 * COST_THREADS];
-    cost_block(P, part, part_idx, nchunk, jbase, jt, diag_dmin, diag_argmin, blockIdx.x * WAVE,
-               lds);
+    cost_block(P, key, key64, jbase, jt, diag_dmin, diag_argmin, blockIdx.x * WAVE, lds);
 }
 
 __global__ __launch_bounds__(256) void k_update(StepArgs P, const float* __restrict__ jt,
@@ -36,17 +35,17 @@ __global__ __launch_bounds__(256) void k_update(StepArgs P, const float* __restr
 }
 
 __global__ __launch_bounds__(64) void k_nominal(StepArgs P, const float* __restrict__ Unew,
-                                                float4* __restrict__ nom) {
+                                                float4* __restrict__ nom,
+                                                unsigned int* __restrict__ key_nom) {
     __shared__ float lds[3 * MPPI_MAX_T_DEV];
-    nominal_block(P, Unew, nom, lds);
+    nominal_block(P, Unew, nom, key_nom, lds);
 }
 
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(
-    StepArgs P, int validate, const float* __restrict__ part_nom, int nchunk,
+    StepArgs P, int validate, const unsigned int* __restrict__ key_nom,
     const float* __restrict__ Unew, float* __restrict__ U, float* __restrict__ out4,
     float* __restrict__ diag_unew, float* __restrict__ diag_dnom) {
-    __shared__ float lds[FIN_THREADS];
-    finalize_block(P, validate, part_nom, nchunk, Unew, U, out4, diag_unew, diag_dnom, lds);
+    finalize_block(P, validate, key_nom, Unew, U, out4, diag_unew, diag_dnom);
 }
 
 }  // namespace
@@ -56,11 +55,11 @@ hipError_t launch_rollout(const StepArgs& P, const float* U, const RolloutOut& o
     return hipGetLastError();
 }
 
-hipError_t launch_cost(const StepArgs& P, const float* part, const int* part_idx, int nchunk,
+hipError_t launch_cost(const StepArgs& P, const unsigned int* key, const unsigned long long* key64,
                        const float* jbase, float* jt, float* diag_dmin, int* diag_argmin,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_cost, dim3(P.Kpad / WAVE), dim3(COST_THREADS), 0, s, P, part, part_idx,
-                       nchunk, jbase, jt, diag_dmin, diag_argmin);
+    hipLaunchKernelGGL(k_cost, dim3(P.Kpad / WAVE), dim3(COST_THREADS), 0, s, P, key, key64, jbase,
+                       jt, diag_dmin, diag_argmin);
     return hipGetLastError();
 }
 
@@ -70,16 +69,17 @@ hipError_t launch_update(const StepArgs& P, const float* jt, const float* eps_ws
     return hipGetLastError();
 }
 
-hipError_t launch_nominal(const StepArgs& P, const float* Unew, float4* nom, hipStream_t s) {
-    hipLaunchKernelGGL(k_nominal, dim3(1), dim3(WAVE), 0, s, P, Unew, nom);
+hipError_t launch_nominal(const StepArgs& P, const float* Unew, float4* nom, unsigned int* key_nom,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_nominal, dim3(1), dim3(WAVE), 0, s, P, Unew, nom, key_nom);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const StepArgs& P, int validate, const float* part_nom, int nchunk,
+hipError_t launch_finalize(const StepArgs& P, int validate, const unsigned int* key_nom,
                            const float* Unew, float* U, float* out4, float* diag_unew,
                            float* diag_dnom, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, P, validate, part_nom, nchunk,
-                       Unew, U, out4, diag_unew, diag_dnom);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, P, validate, key_nom, Unew, U,
+                       out4, diag_unew, diag_dnom);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ namespace emppi {
 
 constexpr int ROLL_HCHUNK = 16;    // horizon steps of controls staged in LDS per chunk
 constexpr int COST_THREADS = 1024; // 64 rollouts x 16 horizon groups
-constexpr int FIN_THREADS = 1024;  // 128 poses x 8 chunk groups
+constexpr int FIN_THREADS = 128;   // one thread per horizon step
 
 // One forward-Euler step q_{h+1} = q_h + F_m(q_h, u_h) dt (Section "Robot
 // Kinematic Models") in the fixed single-precision sequence; (s, c) =
@@ -102,6 +102,8 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
                 seq_sincos(th, s, c);
                 if (P.state_offset) pose = make_float4(x, y, c, s);
                 o.poses[h * Kpad + r] = pose;
+                if (o.key) o.key[h * Kpad + r] = DKEY_INIT;
+                if (o.key64) o.key64[h * Kpad + r] = DKEY64_INIT;
                 if (o.diag_poses && live) {
                     float* dp = o.diag_poses + (static_cast<size_t>(r) * T + h) * 4;
                     dp[0] = pose.x;
@@ -118,31 +120,30 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
 }
 
 // J~ of rollouts [r0, r0 + 64) (Algorithm 1 steps 2-3): lane l, group q of
-// the 1024 threads merges the chunk minima of (r0 + l, h) for h = q, q + 16,
-// ..., adds the obstacle penalties and the unsafe flag; the 16 partial sums
-// are added in index order.  lds: 2 * 1024 words.
-__device__ __forceinline__ void cost_block(const StepArgs& P, const float* __restrict__ part,
-                                           const int* __restrict__ part_idx, int nchunk,
+// the 1024 threads decodes the minimum of (r0 + l, h) for h = q, q + 16, ...,
+// adds the obstacle penalties and the unsafe flag; the 16 partial sums are
+// added in index order.  lds: 2 * 1024 words.
+__device__ __forceinline__ void cost_block(const StepArgs& P, const unsigned int* __restrict__ key,
+                                           const unsigned long long* __restrict__ key64,
                                            const float* __restrict__ jbase, float* __restrict__ jt,
                                            float* __restrict__ diag_dmin,
                                            int* __restrict__ diag_argmin, int r0, float* lds) {
     const int lane = threadIdx.x & (WAVE - 1), grp = threadIdx.x / WAVE;
     const int ngrp = blockDim.x / WAVE;
     const int r = r0 + lane;
-    const size_t npose = static_cast<size_t>(P.T) * P.Kpad;
     float J = 0.0f;
     int chi = 0;
     if (r < P.K) {
         for (int h = grp; h < P.T; h += ngrp) {
             const size_t g = static_cast<size_t>(h) * P.Kpad + r;
-            float sq = part[g];
-            int idx = part_idx ? part_idx[g] : -1;
-            for (int k = 1; k < nchunk; ++k) {
-                const float v = part[k * npose + g];
-                if (v < sq) {
-                    sq = v;
-                    if (part_idx) idx = part_idx[k * npose + g];
-                }
+            float sq;
+            int idx = -1;
+            if (key64) {
+                const unsigned long long k = key64[g];
+                sq = dkey_value(static_cast<unsigned int>(k >> 32));
+                idx = static_cast<int>(static_cast<unsigned int>(k));
+            } else {
+                sq = dkey_value(key[g]);
             }
             const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
             const float gap = fmaxf(P.d_safe - d, 0.0f);
@@ -224,10 +225,13 @@ __device__ __forceinline__ void update_block(const StepArgs& P, const float* __r
 
 // Nominal trajectory of the updated sequence (Algorithm 1 step 4) in the same
 // single-precision sequence as the sampled rollouts.  The sequence is first
-// copied to LDS (lds: 3 * MPPI_MAX_T floats), then lane 0 integrates.
+// copied to LDS (lds: 3 * MPPI_MAX_T floats), then lane 0 integrates; the
+// distance keys of the T nominal poses are initialised on the way.
 __device__ __forceinline__ void nominal_block(const StepArgs& P, const float* __restrict__ Unew,
-                                              float4* __restrict__ nom, float* lds) {
+                                              float4* __restrict__ nom,
+                                              unsigned int* __restrict__ key_nom, float* lds) {
     for (int k = threadIdx.x; k < P.T * P.nu; k += blockDim.x) lds[k] = Unew[k];
+    for (int h = threadIdx.x; h < P.T; h += blockDim.x) key_nom[h] = DKEY_INIT;
     __syncthreads();
     if (threadIdx.x != 0) return;
     float x = P.q0[0], y = P.q0[1], th = P.q0[2], s, c;
@@ -245,39 +249,31 @@ __device__ __forceinline__ void nominal_block(const StepArgs& P, const float* __
 
 // Validation and execution (Algorithm 1 step 4): valid iff every
 // d_nom >= d_safe; then u* = U_0 and U shifts left (last entry repeated),
-// else u* = 0 and U = 0.  out4 = (u*_0, u*_1, u*_2, valid).  1024 threads:
-// pose h = tid % 128 merges chunk group tid / 128 (min is exact, so any
-// grouping gives the same value).  lds: 1024 floats.
+// else u* = 0 and U = 0.  out4 = (u*_0, u*_1, u*_2, valid).  One thread per
+// horizon step (MPPI_MAX_T_DEV threads).
 __device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
-                                               const float* __restrict__ part_nom, int nchunk,
+                                               const unsigned int* __restrict__ key_nom,
                                                const float* __restrict__ Unew,
                                                float* __restrict__ U, float* __restrict__ out4,
                                                float* __restrict__ diag_unew,
-                                               float* __restrict__ diag_dnom, float* lds) {
-    const int T = P.T, nu = P.nu;
-    const int h = threadIdx.x % MPPI_MAX_T_DEV, grp = threadIdx.x / MPPI_MAX_T_DEV;
-    const int ngrp = blockDim.x / MPPI_MAX_T_DEV;
-    float sq = INFINITY;
-    if (validate && h < T)
-        for (int k = grp; k < nchunk; k += ngrp) sq = fminf(sq, part_nom[k * T + h]);
-    lds[threadIdx.x] = sq;
-    __syncthreads();
+                                               float* __restrict__ diag_dnom) {
+    const int T = P.T, nu = P.nu, h = threadIdx.x;
     int bad = 0;
-    if (validate && grp == 0 && h < T) {
-        for (int q = 1; q < ngrp; ++q) sq = fminf(sq, lds[q * MPPI_MAX_T_DEV + h]);
+    if (validate && h < T) {
+        const float sq = dkey_value(key_nom[h]);
         const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
         bad = !(d >= P.d_safe);
         if (diag_dnom) diag_dnom[h] = d;
     }
     const int ok = !__syncthreads_or(bad);
-    if (grp == 0 && h < T) {
+    if (h < T) {
         const int src = (h + 1 < T ? h + 1 : T - 1) * nu;
         for (int k = 0; k < nu; ++k) {
             if (diag_unew) diag_unew[h * nu + k] = Unew[h * nu + k];
             U[h * nu + k] = ok ? Unew[src + k] : 0.0f;
         }
     }
-    if (threadIdx.x == 0) {
+    if (h == 0) {
         for (int k = 0; k < 3; ++k) out4[k] = (ok && k < nu) ? Unew[k] : 0.0f;
         out4[3] = ok ? 1.0f : 0.0f;
     }

@@ -1,0 +1,207 @@
+"""Training data, training and evaluation of the learned sampling proposal.
+
+Every arithmetic step runs in the library's kernels (MPPI steps, features,
+forward / backward passes, Adam); this module only orchestrates them.
+
+* Data: closed-loop plain MPPI (K = 4096) on Ackermann corridor scenes with
+  the in-corridor clutter thinned, many episodes stepped together through the
+  batched step.  For a validated step the updated nominal is recovered exactly
+  from its outputs (u* = U_upd[0], and the shifted nominal holds U_upd[1:]);
+  held (invalid) steps carry no target and are skipped.  Sample = (features
+  of the state before the step, updated nominal scaled to [-1, 1]).
+* Training: minibatch Adam on the mean squared error.
+* Evaluation: for held-out states, one MPPI update from (a) the plain shifted
+  nominal with K = 4096, (b) the same with K = 1024, (c) the network's mean
+  with K = 1024 (falling back to the shifted nominal when the mean's
+  noise-free cost is higher); the score of an update is the noise-free
+  augmented cost of the updated nominal (a K = 1, sigma = 0 rollout).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+import paper_2605_29663_amd as pkg
+from paper_2605_29663_amd import scenes
+
+TRAIN_SEED0 = 10 ** 6
+HELDOUT_SEED0 = 2 * 10 ** 6
+
+
+def scene_params(sc, K):
+    p = scenes.params("c2", K=K)
+    p["goal"] = tuple(float(g) for g in sc["goal"])
+    return p
+
+
+def corridor_scene(seed):
+    return scenes.scene_c2(seed=seed, clutter_keep=0.1)
+
+
+def make_context(sc):
+    c = pkg.Context(0)
+    c.set_footprint(pkg.POLYGON, sc["polygon"])
+    c.set_points(sc["ox"], sc["oy"])
+    return c
+
+
+def propagate(q, u, dt, L):
+    """The simulated robot: one Euler step of the Ackermann model (double)."""
+    x, y, th = (float(v) for v in q)
+    v, d = float(u[0]), float(u[1])
+    return np.array([x + v * math.cos(th) * dt, y + v * math.sin(th) * dt,
+                     th + v / L * math.tan(d) * dt], dtype=np.float32)
+
+
+class Episodes:
+    """n corridor episodes stepped together with the batched plain MPPI step."""
+
+    def __init__(self, seeds, K):
+        self.scenes = [corridor_scene(s) for s in seeds]
+        self.prms = [scene_params(sc, K) for sc in self.scenes]
+        self.ctxs = [make_context(sc) for sc in self.scenes]
+        self.batch = pkg.Batch(self.ctxs, self.prms)
+        self.U = self.batch.new_nominals()
+        self.q = np.zeros((len(seeds), 3), dtype=np.float32)
+        self.seeds = np.array(seeds, dtype=np.uint64)
+        self.t = 0
+
+    def step(self):
+        """One batched step; returns (q before, U before [n, T, 2] device, u*, valid, U after)."""
+        n = len(self.scenes)
+        T = self.prms[0]["T"]
+        q_before = self.q.copy()
+        U_before = self.U.view(n, T, 2).clone()
+        steps = np.full(n, self.t, dtype=np.uint64)
+        u, valid = self.batch.mppi_step_batched(self.q, self.U, self.seeds, steps, use_graph=True)
+        for s in range(n):
+            p = self.prms[s]
+            self.q[s] = propagate(self.q[s], u[s], p["dt"], p["wheelbase"])
+        self.t += 1
+        return q_before, U_before, u, valid, self.U.view(n, T, 2)
+
+
+def generate(n_samples, n_parallel=64, steps_per_episode=200, K=4096, seed0=TRAIN_SEED0,
+             net=None, log=print, max_seconds=None):
+    """Features and scaled targets of (up to) n_samples validated plain-MPPI steps,
+    stopping early after max_seconds."""
+    T = 40
+    if net is None:
+        net = pkg.Proposal(T, 2, hidden=256, max_batch=1024)
+    feats, targets = [], []
+    have, ep = 0, 0
+    t0 = time.time()
+    while have < n_samples:
+        E = Episodes([seed0 + ep * n_parallel + s for s in range(n_parallel)], K)
+        for t in range(steps_per_episode):
+            qb, Ub, u, valid, Ua = E.step()
+            for s in np.flatnonzero(valid):
+                net.set_scaling(E.prms[s])
+                f = net.features(E.ctxs[s], torch.tensor(qb[s:s + 1], device="cuda"), Ub[s:s + 1])
+                U_upd = torch.cat([torch.tensor(u[s:s + 1, :2], device="cuda"), Ua[s, :-1]], 0)
+                feats.append(f)
+                targets.append(net.normalize(U_upd.contiguous()))
+            have += int(valid.sum())
+            if have >= n_samples or (max_seconds and time.time() - t0 > max_seconds):
+                break
+            if t % 20 == 0:
+                log(f"generate: episode group {ep} step {t}: {have} samples, {time.time() - t0:.0f} s")
+        E.batch.close()
+        ep += 1
+        if max_seconds and time.time() - t0 > max_seconds:
+            break
+    X = torch.cat(feats)[:n_samples].contiguous()
+    Y = torch.cat(targets)[:n_samples].contiguous()
+    return X, Y
+
+
+def train(net, X, Y, epochs=30, batch=1024, lr=1e-3, lr_final=1e-4, seed=0, log=print):
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    steps = epochs * (n // batch)
+    k = 0
+    losses = []
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(n), device="cuda")
+        tot = 0.0
+        for b in range(n // batch):
+            idx = perm[b * batch:(b + 1) * batch]
+            a = k / max(1, steps - 1)
+            lr_k = lr * (lr_final / lr) ** a
+            tot += net.train_step(X[idx].contiguous(), Y[idx].contiguous(), lr_k)
+            k += 1
+        losses.append(tot / max(1, n // batch))
+        log(f"train: epoch {ep} loss {losses[-1]:.5f}")
+    return losses
+
+
+def nominal_cost(ctx, prm, q, U):
+    """Noise-free augmented cost of one control sequence (K = 1, sigma = 0 rollout)."""
+    p = dict(prm, K=1, sigma=(0.0, 0.0), validate=0)
+    Uc = U.clone().contiguous()
+    _, _, D = ctx.mppi_step(p, q, Uc, 0, 0, diag=True)
+    return float(D["J"][0].item())
+
+
+def evaluate(net, n_states=1000, n_parallel=64, warm_steps=40, seed0=HELDOUT_SEED0,
+             K_big=4096, K_small=1024, log=print):
+    """Held-out comparison; returns per-state costs (plain_big, plain_small, learned)."""
+    rows = []
+    ep = 0
+    t0 = time.time()
+    while len(rows) < n_states:
+        E = Episodes([seed0 + ep * n_parallel + s for s in range(n_parallel)], K_big)
+        t = 0
+        while len(rows) < n_states and t < warm_steps + 200:
+            qb, Ub, u, valid, Ua = E.step()
+            t += 1
+            if t <= warm_steps or t % 5:
+                continue
+            for s in range(n_parallel):
+                if len(rows) >= n_states:
+                    break
+                ctx, p = E.ctxs[s], E.prms[s]
+                q = qb[s]
+                seed = int(seed0 + 7919 * len(rows))
+                # (a), (b): plain updates from the shifted nominal
+                res = []
+                for K in (K_big, K_small):
+                    U = Ub[s].clone().contiguous()
+                    _, _, D = ctx.mppi_step(dict(p, K=K, validate=0), q, U, seed, 0, diag=True)
+                    res.append(nominal_cost(ctx, p, q, D["U_upd"]))
+                # (c): learned mean, fallback to the shifted nominal
+                net.set_scaling(p)
+                f = net.features(ctx, torch.tensor(q[None], device="cuda"), Ub[s:s + 1])
+                mu = net.mean(f)[0].contiguous()
+                if nominal_cost(ctx, p, q, mu) > nominal_cost(ctx, p, q, Ub[s]):
+                    mu = Ub[s].clone().contiguous()
+                _, _, D = ctx.mppi_step(dict(p, K=K_small, validate=0), q, mu, seed, 0, diag=True)
+                res.append(nominal_cost(ctx, p, q, D["U_upd"]))
+                rows.append(res)
+            log(f"evaluate: {len(rows)} states, {time.time() - t0:.0f} s")
+        E.batch.close()
+        ep += 1
+    return np.array(rows)
+
+
+def summarize(costs, seed=0, n_boot=2000):
+    """Mean cost ratios learned / plain@big and plain@small / plain@big, with
+    bootstrap 95 % intervals, and learned / plain@small (the gain at equal K)."""
+    rng = np.random.default_rng(seed)
+    big, small, learned = costs[:, 0], costs[:, 1], costs[:, 2]
+
+    def ratio(a, b):
+        r = float(a.mean() / b.mean())
+        idx = rng.integers(0, len(a), (n_boot, len(a)))
+        bs = a[idx].mean(1) / b[idx].mean(1)
+        return {"ratio": r, "ci95": [float(np.percentile(bs, 2.5)), float(np.percentile(bs, 97.5))]}
+
+    return {"n_states": int(len(costs)),
+            "learned_small_over_plain_big": ratio(learned, big),
+            "plain_small_over_plain_big": ratio(small, big),
+            "learned_small_over_plain_small": ratio(learned, small),
+            "mean_cost": {"plain_big": float(big.mean()), "plain_small": float(small.mean()),
+                          "learned_small": float(learned.mean())}}

@@ -1,0 +1,56 @@
+"""Train and evaluate the learned sampling proposal on the GPU.
+
+    python -m paper_2605_29663_amd.train_proposal --samples 50000 --out DIR
+
+Writes DIR/proposal_c2.bin (weights + Adam state), DIR/proposal_c2_eval.json
+(held-out cost ratios) and prints progress lines.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--samples", type=int, default=50000)
+    ap.add_argument("--parallel", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--eval-states", type=int, default=1000)
+    ap.add_argument("--out", default=".")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-data-seconds", type=float, default=420.0)
+    args = ap.parse_args()
+    import torch
+    import paper_2605_29663_amd as pkg
+    from paper_2605_29663_amd import learn
+
+    def log(msg):
+        print(msg, flush=True)
+
+    os.makedirs(args.out, exist_ok=True)
+    t0 = time.time()
+    net = pkg.Proposal(40, 2, hidden=256, max_batch=1024)
+    X, Y = learn.generate(args.samples, n_parallel=args.parallel, net=net, log=log,
+                          max_seconds=args.max_data_seconds)
+    log(f"data: {X.shape[0]} samples in {time.time() - t0:.0f} s")
+    net.init_params(args.seed)
+    t1 = time.time()
+    losses = learn.train(net, X, Y, epochs=args.epochs, log=log)
+    log(f"train: {time.time() - t1:.0f} s, final loss {losses[-1]:.5f}")
+    net.save(os.path.join(args.out, "proposal_c2.bin"))
+    t2 = time.time()
+    costs = learn.evaluate(net, n_states=args.eval_states, n_parallel=args.parallel, log=log)
+    summary = learn.summarize(costs)
+    summary.update(samples=int(X.shape[0]), epochs=args.epochs, train_loss=losses,
+                   seconds={"data": t1 - t0, "train": t2 - t1, "eval": time.time() - t2})
+    with open(os.path.join(args.out, "proposal_c2_eval.json"), "w") as f:
+        json.dump(summary, f, indent=1)
+    log(json.dumps({k: v for k, v in summary.items() if k != "train_loss"}))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
