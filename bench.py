@@ -43,12 +43,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"],
+                    help="c1/c2/c3: single-scene step; c4: 64-scene batched step (graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the tile shapes instead of using the shipped table")
     ap.add_argument("--cpu-reps", type=int, default=4,
                     help="whole oracle steps timed for the CPU baseline")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (5 times), "
+                         "the reference kernel for scaling the HBM byte counters")
     return ap.parse_args()
 
 
@@ -59,17 +63,113 @@ def padded_count(kind, count):
     return next(b for b in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32) if count <= b)
 
 
-def traffic_record(kernel_src, workload):
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_29663_amd", "csrc", f)
+                  for f in ("kernels_sdf.hip", "kernels_batch.hip", "sdf_device.hpp", "kernels.hpp")]
+
+
+def kernel_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def traffic_record(workload):
     """HBM bytes per launch measured by rocprofv3 counters, if they were taken on
-    the current source of the kernel (sha256 recorded next to the numbers)."""
+    the current source of the distance kernels (sha256 recorded with the numbers)."""
     path = os.path.join(ROOT, "profiles", f"dmin_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if rec.get("kernel_sha256") != sha:
+    if rec.get("kernel_sha256") != kernel_sha256():
         return None
     return rec.get("bytes_per_launch")
+
+
+def copy_probe(mib):
+    """A plain copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "launches": 5}))
+
+
+def run_batched(args):
+    """64 uneven scenes in one batched step, replayed from the captured graph."""
+    import numpy as np
+    import torch
+    import paper_2605_29663_amd as pkg
+    from paper_2605_29663_amd import scenes
+
+    cases = scenes.batch_scenes(64)
+    ctxs = []
+    for prm, sc in cases:
+        c = pkg.Context(0)
+        c.set_footprint(pkg.POLYGON, sc["polygon"])
+        c.set_points(sc["ox"], sc["oy"])
+        ctxs.append(c)
+    b = pkg.Batch(ctxs, [p for p, _ in cases])
+    work = b.mppi_batch_autotune(reps=2)
+    n = len(cases)
+    U = b.new_nominals()
+    q0 = np.zeros((n, 3), np.float32)
+    seeds = np.arange(1000, 1000 + n, dtype=np.uint64)
+    for i in range(args.warmup):
+        b.mppi_step_batched(q0, U, seeds, np.full(n, i, np.uint64), use_graph=True)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        b.mppi_step_batched(q0, U, seeds, np.full(n, args.warmup + i, np.uint64), use_graph=True)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the distance pass timed with HIP events on eager steps of the same batch
+    b.set_profiling(True)
+    n_eager = max(3, min(args.steps, 10))
+    for i in range(n_eager):
+        b.mppi_step_batched(q0, U, seeds, np.full(n, 10 ** 6 + i, np.uint64), use_graph=False)
+    k_ms, k_n = b.get_profile()
+    b.set_profiling(False)
+    Ks = np.array([p["K"] for p, _ in cases], np.float64)
+    Ts = np.array([p["T"] for p, _ in cases], np.float64)
+    Ns = np.array([sc["ox"].size for _, sc in cases], np.float64)
+    Bs = np.array([len(sc["polygon"]) for _, sc in cases], np.float64)
+    pairs_main = float(np.sum(Ks * Ts * Ns * Bs))
+    pairs_step = pairs_main + float(np.sum(Ts * Ns * Bs))
+    per_unit, per_pose_point = OPS[0]
+    ops = pairs_main * per_unit + float(np.sum(Ks * Ts * Ns)) * per_pose_point
+    k_avg = k_ms / max(k_n, 1)
+    achieved = ops / (k_avg / 1e3) / 1e12
+    items_main, items_val, _ = b.mppi_batch_info()
+    out = {
+        "metric": "SDF evals/s (K*T*N*edges per MPPI step) and MPPI step latency",
+        "value": pairs_step / (ms_step / 1e3), "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p95": float(np.percentile(lat, 95) * 1e3)},
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded scene generator)",
+        "config": {"workload": "64 uneven scenes, batched persistent launch in a hipGraph",
+                   "scenes": n, "pairs_per_step": pairs_step,
+                   "K": "512..4096", "T": "20..60", "N": "1e3..3e4", "B": "4..32",
+                   "motion_model": "unicycle / ackermann"},
+        "roofline": {"bound": "alu", "kernel": "k_dmin_persistent (sampled-rollout pass)",
+                     "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": traffic_record("c4"), "kernel_ms": k_avg, "launches": k_n,
+                     "timing": "HIP events around the persistent launches of eager steps",
+                     "tiles": {"pairs_per_item": work, "items_main": items_main,
+                               "items_validation": items_val, "source": "batch autotuner"}},
+    }
+    print(json.dumps(out))
+    b.close()
 
 
 def main():
@@ -79,6 +179,12 @@ def main():
                                    "described in DESIGN.md and not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
+    if args.config == "c4":
+        run_batched(args)
+        return
     import numpy as np
     import torch
     import paper_2605_29663_amd as pkg
@@ -136,7 +242,6 @@ def main():
     ops_launch = pairs_main * per_unit + K * T * N * per_pose_point
     k_avg_ms = k_ms / max(k_n, 1)
     achieved = ops_launch / (k_avg_ms / 1e3) / 1e12
-    kernel_src = os.path.join(ROOT, "paper_2605_29663_amd", "csrc", "kernels_sdf.hip")
     workload = args.config
 
     out = {
@@ -161,7 +266,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_dmin_poly" if kind == 0 else "k_dmin_rect",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": traffic_record(kernel_src, workload),
+                     "traffic": traffic_record(workload),
                      "kernel_ms": k_avg_ms, "launches": k_n,
                      "tiles": {"block": tuned[0], "chunks": tuned[1], "source": tile_source}},
     }

@@ -97,7 +97,11 @@ typedef struct mppi_params {
  *   eps     K*T*nu: clipped perturbation eps_eff
  *   u       K*T*nu: sampled (clipped) control
  *   U_upd   T*nu: nominal after the weighted update, before validation
- *   d_nom   T: minimum signed distance along the updated nominal          */
+ *   d_nom   T: minimum signed distance along the updated nominal
+ *   J_nom   1: noise-free cost of the updated nominal, the sum over its
+ *              validation rollout of the same per-step terms as J (task,
+ *              control and obstacle terms; + w_inf if some d_nom < d_safe);
+ *              NaN when validation is off                                   */
 typedef struct mppi_diag {
     float* d_min;
     int32_t* argmin;
@@ -108,6 +112,7 @@ typedef struct mppi_diag {
     float* u;
     float* U_upd;
     float* d_nom;
+    float* J_nom;
 } mppi_diag;
 
 /* Create a context on HIP device `device`; work is issued on `hip_stream`
@@ -293,6 +298,71 @@ MPPI_API int mppi_batch_autotune(mppi_batch b, int reps, double* out_work_per_it
  * NULL.                                                                     */
 MPPI_API int mppi_batch_info(mppi_batch b, long long* items_main, long long* items_validation,
                              double* work_per_item);
+
+/* J_nom (see mppi_diag) of every scene from the last batched step: host n. */
+MPPI_API int mppi_batch_nominal_costs(mppi_batch b, float* J_out);
+
+/* Timing of the sampled-rollout signed-distance pass (all persistent
+ * launches of one step, HIP events on the batch's stream) over the eager
+ * steps (use_graph = 0) run since profiling was enabled; graph replays are
+ * not timed.  get: total milliseconds and number of timed steps.           */
+MPPI_API int mppi_batch_set_profiling(mppi_batch b, int enable);
+MPPI_API int mppi_batch_get_profile(mppi_batch b, double* ms, long long* launches);
+
+/* ------------------------------------------------------------------------
+ * Hybrid-mode cycle (Section "Extension to Hybrid-Mode Platforms",
+ * Algorithm 2): one Algorithm-1 cycle per motion mode (each mode its own
+ * rollout family and nominal sequence, the footprint and points shared),
+ * all modes in one batched launch, then a device-side selection:
+ *   Jbar_m = J_m + lambda_switch [m != m_prev] if mode m validated, else +inf,
+ *   where J_m is the mode's J_nom (see mppi_diag);
+ *   no mode validated -> safe stop: zero command, mode stays m_prev;
+ *   m* = argmin Jbar (lowest index on ties), kept at m_prev while the
+ *   cooldown tau_cool > 0; tau_cool <- cool_max after a switch, else
+ *   max(tau_cool - 1, 0);
+ *   command = mode m*'s executed command u* in that mode's own command
+ *   layout (v, delta) / (v, omega) / (vx, vy, omega) / (omega) / (v_para),
+ *   with the deadzone correction: translational modes scale the linear part
+ *   (v, or (vx, vy)) up to v_min when noise_v < |v| < v_min; spin-in-place
+ *   sets |omega| to w_min (sign kept) when noise_w < |omega| < w_min.
+ * ------------------------------------------------------------------------ */
+typedef struct mppi_hybrid_s* mppi_hybrid;
+
+typedef struct mppi_hybrid_params {
+    float lambda_switch;  /* switching penalty, >= 0                          */
+    int32_t cool_max;     /* cooldown length after a switch (cycles), >= 0    */
+    float v_min, w_min;   /* minimum executable speed / yaw rate, >= 0        */
+    float noise_v, noise_w; /* below these magnitudes no correction is made   */
+} mppi_hybrid_params;
+
+enum { MPPI_MAX_MODES = 8 };
+
+/* Create the mode set over context `scene` (footprint and points are read
+ * from it at every step; it must outlive the hybrid object): modes[m] are
+ * full Algorithm-1 parameter sets (host, copied; their `model` selects the
+ * dynamics, each must have validate = 1).  1 <= n_modes <= MPPI_MAX_MODES.
+ * Noise of mode m uses Philox stream word m.  Errors as mppi_batch_create
+ * (message via mppi_hybrid_last_error(NULL)).                              */
+MPPI_API int mppi_hybrid_create(mppi_hybrid* out, mppi_ctx scene, const mppi_params* modes,
+                                int n_modes, void* hip_stream);
+MPPI_API int mppi_hybrid_destroy(mppi_hybrid h);
+MPPI_API const char* mppi_hybrid_last_error(mppi_hybrid h);
+/* The underlying batch (for mppi_batch_u_offsets / refresh / autotune).   */
+MPPI_API mppi_batch mppi_hybrid_batch(mppi_hybrid h);
+
+/* One hybrid cycle.  q0: host 3.  dU: device packed per-mode nominals
+ * (layout of mppi_batch_u_offsets), updated in place by each mode's cycle.
+ * seed, step: as mppi_step.  m_prev, tau_cool: host in/out (the selected
+ * mode and the new cooldown on return).  u_out: host 3 (unused channels 0).
+ * stopped (may be NULL): 1 for a safe stop.  J_modes, valid_modes (host
+ * n_modes each, may be NULL): each mode's J_m and validation flag.
+ * use_graph as mppi_step_batched.  Synchronous.  Errors: MPPI_E_ARG
+ * (m_prev out of range, negative cooldown or thresholds), MPPI_E_STATE,
+ * MPPI_E_HIP.                                                              */
+MPPI_API int mppi_hybrid_step(mppi_hybrid h, const float q0[3], float* dU, uint64_t seed,
+                              uint64_t step, const mppi_hybrid_params* hp, int* m_prev,
+                              int* tau_cool, float u_out[3], int* stopped, float* J_modes,
+                              int* valid_modes, int use_graph);
 
 /* ------------------------------------------------------------------------
  * Learned sampling proposal (not part of the paper's method, which is

@@ -12,6 +12,7 @@ dict can be handed to the HIP binding and to the oracle.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -351,7 +352,11 @@ def mppi_step(prm, q0, U, scene, seed, step, stream=0):
         dn = dmin(npose, tau_of(prm, T), scene["ox"], scene["oy"], scene.get("ovx"),
                   scene.get("ovy"), scene.get("valid"), kind, geom)
         ok, ustar, Unext = validate_shift(Un, dn, prm["d_safe"])
-        out.update(d_nom=dn, valid=ok, u_star=ustar, U_next=Unext)
+        # noise-free cost of the updated nominal: the terms of J along its
+        # validation rollout (+ w_inf when unsafe); Algorithm 2 compares it
+        # across motion modes
+        J_nom = costs(prm, st[None, :, :2], Un[None], dn[None])[2][0]
+        out.update(d_nom=dn, valid=ok, u_star=ustar, U_next=Unext, J_nom=J_nom, nom_states=st)
     else:
         out.update(valid=True, u_star=Un[0].copy(), U_next=np.concatenate([Un[1:], Un[-1:]]))
     return out
@@ -368,3 +373,54 @@ def f32_features(ox, oy, valid, q0, goal, U_prev, u_min, u_max, r_max=8.0):
                            _p(U_prev), T, nu, _p(_vec3(u_min, -1.0)), _p(_vec3(u_max, 1.0)),
                            np.float32(r_max), _p(out))
     return out
+
+
+# --------------------------------------------------------------------------
+# Hybrid-mode cycle (Section "Extension to Hybrid-Mode Platforms", Algorithm 2)
+# --------------------------------------------------------------------------
+SPIN = 3
+OMNI = 2
+
+
+def hybrid_select(J, valid, u_star, models, m_prev, tau_cool, hp):
+    """Mode selection with cooldown and the actuator post-processing.
+
+    J, valid, u_star: each mode's cycle result (J_m = its J_nom, validation
+    flag, executed command in the mode's own layout).  Returns
+    (u, m_star, tau_cool', stopped).
+    """
+    n = len(J)
+    Jbar = [J[m] + (hp["lambda_switch"] if m != m_prev else 0.0) if valid[m] else math.inf
+            for m in range(n)]
+    if all(j == math.inf for j in Jbar):
+        return np.zeros(3), m_prev, tau_cool, True          # safe stop
+    m_star = min(range(n), key=lambda m: (Jbar[m], m))
+    if tau_cool > 0 and m_star != m_prev:
+        m_star = m_prev
+    tau_new = hp["cool_max"] if m_star != m_prev else max(tau_cool - 1, 0)
+    u = np.zeros(3)
+    u[:len(u_star[m_star])] = u_star[m_star]
+    model = models[m_star]
+    if model != SPIN:                                        # translational mode
+        nlin = 2 if model == OMNI else 1
+        vmag = math.sqrt(sum(float(u[k]) ** 2 for k in range(nlin)))
+        if hp["noise_v"] < vmag < hp["v_min"]:
+            u[:nlin] *= hp["v_min"] / vmag
+    else:                                                    # pure rotation
+        w = float(u[0])
+        if hp["noise_w"] < abs(w) < hp["w_min"]:
+            u[0] = math.copysign(hp["w_min"], w)
+    return u, m_star, tau_new, False
+
+
+def hybrid_step(mode_prms, q0, Us, scene, seed, step, m_prev, tau_cool, hp):
+    """One Algorithm-2 cycle from scratch: an Algorithm-1 cycle per mode
+    (mode m draws noise on stream m), then hybrid_select."""
+    res = [mppi_step(p, q0, U, scene, seed, step, stream=m)
+           for m, (p, U) in enumerate(zip(mode_prms, Us))]
+    J = [r["J_nom"] for r in res]
+    valid = [r["valid"] for r in res]
+    u_star = [r["u_star"] for r in res]
+    models = [MODELS[p["model"]] if isinstance(p["model"], str) else p["model"] for p in mode_prms]
+    u, m, tau, stopped = hybrid_select(J, valid, u_star, models, m_prev, tau_cool, hp)
+    return dict(u=u, mode=m, tau_cool=tau, stopped=stopped, modes=res)

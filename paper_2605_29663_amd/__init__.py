@@ -31,7 +31,10 @@ EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footpri
            "mppi_set_profiling", "mppi_get_profile",
            "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
            "mppi_batch_u_offsets", "mppi_batch_refresh", "mppi_step_batched",
-           "mppi_batch_autotune", "mppi_batch_info",
+           "mppi_batch_autotune", "mppi_batch_info", "mppi_batch_nominal_costs",
+           "mppi_batch_set_profiling", "mppi_batch_get_profile",
+           "mppi_hybrid_create", "mppi_hybrid_destroy", "mppi_hybrid_last_error",
+           "mppi_hybrid_batch", "mppi_hybrid_step",
            "proposal_create", "proposal_destroy", "proposal_last_error", "proposal_num_params",
            "proposal_shape", "proposal_set_params", "proposal_get_params", "proposal_set_scaling",
            "proposal_features", "proposal_forward", "proposal_mean", "proposal_normalize",
@@ -56,9 +59,19 @@ class MppiParams(ctypes.Structure):
                 ("validate", ctypes.c_int32)]
 
 
+class HybridParams(ctypes.Structure):
+    _fields_ = [("lambda_switch", ctypes.c_float), ("cool_max", ctypes.c_int32),
+                ("v_min", ctypes.c_float), ("w_min", ctypes.c_float),
+                ("noise_v", ctypes.c_float), ("noise_w", ctypes.c_float)]
+
+
 class MppiDiag(ctypes.Structure):
+    @classmethod
+    def names(cls):
+        return [f[0] for f in cls._fields_]
+
     _fields_ = [(n, ctypes.c_void_p) for n in
-                ("d_min", "argmin", "J", "w", "poses", "eps", "u", "U_upd", "d_nom")]
+                ("d_min", "argmin", "J", "w", "poses", "eps", "u", "U_upd", "d_nom", "J_nom")]
 
 
 _lib = None
@@ -106,6 +119,19 @@ def load():
     L.mppi_batch_autotune.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
     L.mppi_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
+    L.mppi_batch_nominal_costs.argtypes = [vp, vp]
+    L.mppi_batch_set_profiling.argtypes = [vp, i]
+    L.mppi_batch_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_longlong)]
+    L.mppi_hybrid_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(MppiParams), i, vp]
+    L.mppi_hybrid_destroy.argtypes = [vp]
+    L.mppi_hybrid_last_error.argtypes = [vp]
+    L.mppi_hybrid_last_error.restype = ctypes.c_char_p
+    L.mppi_hybrid_batch.argtypes = [vp]
+    L.mppi_hybrid_batch.restype = vp
+    L.mppi_hybrid_step.argtypes = [vp, vp, vp, u64, u64, ctypes.POINTER(HybridParams),
+                                   ctypes.POINTER(i), ctypes.POINTER(i), vp, ctypes.POINTER(i),
+                                   vp, vp, i]
     ll = ctypes.c_longlong
     L.proposal_create.argtypes = [ctypes.POINTER(vp), i, vp, i, i, i, i]
     L.proposal_destroy.argtypes = [vp]
@@ -313,9 +339,9 @@ class Context:
                        eps=torch.empty((K, T, nu), device=dev),
                        u=torch.empty((K, T, nu), device=dev),
                        U_upd=torch.empty((T, nu), device=dev),
-                       d_nom=torch.full((T,), math.nan, device=dev))
-            D = MppiDiag(*[out[k].data_ptr() for k in
-                           ("d_min", "argmin", "J", "w", "poses", "eps", "u", "U_upd", "d_nom")])
+                       d_nom=torch.full((T,), math.nan, device=dev),
+                       J_nom=torch.full((1,), math.nan, device=dev))
+            D = MppiDiag(*[out[k].data_ptr() for k in MppiDiag.names()])
         q = (ctypes.c_float * 3)(*[float(v) for v in q0])
         u_out = (ctypes.c_float * 3)()
         valid = ctypes.c_int(0)
@@ -405,6 +431,92 @@ class Batch:
             u_out.ctypes.data_as(vp), valid.ctypes.data_as(vp), int(bool(use_graph))))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return u_out, valid.astype(bool)
+
+    def set_profiling(self, enable=True):
+        self._check(self.lib.mppi_batch_set_profiling(self.h, int(bool(enable))))
+
+    def get_profile(self):
+        """(total ms, timed eager steps) of the sampled-rollout distance pass."""
+        ms, n = ctypes.c_double(), ctypes.c_longlong()
+        self._check(self.lib.mppi_batch_get_profile(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def nominal_costs(self):
+        """J_nom of every scene from the last step (NaN where validation is off)."""
+        J = np.zeros(self.n, dtype=np.float32)
+        self._check(self.lib.mppi_batch_nominal_costs(self.h, J.ctypes.data_as(ctypes.c_void_p)))
+        return J
+
+
+class Hybrid:
+    """Hybrid-mode cycle (Algorithm 2) over one context: one parameter set per
+    motion mode.  Runs on its own torch stream, ordered after the caller's."""
+
+    def __init__(self, context, mode_params):
+        self.lib = load()
+        self.context = context
+        self.params = (MppiParams * len(mode_params))(*[make_params(p) for p in mode_params])
+        self.n = len(mode_params)
+        self.device = context.device
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.mppi_hybrid_create(ctypes.byref(h), context.h, self.params, self.n,
+                                         ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.mppi_hybrid_last_error(None).decode())
+        self.h = h
+        off = (ctypes.c_int * (self.n + 1))()
+        rc = self.lib.mppi_batch_u_offsets(self.lib.mppi_hybrid_batch(self.h), off)
+        self._check(rc)
+        self.u_offsets = list(off)
+
+    def _check(self, rc):
+        if rc != MPPI_OK:
+            raise MppiError(rc, self.lib.mppi_hybrid_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mppi_hybrid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_nominals(self):
+        return torch.zeros(max(1, self.u_offsets[-1]), dtype=torch.float32, device=self.device)
+
+    def nominal(self, U, m):
+        p = self.params[m]
+        return U[self.u_offsets[m]:self.u_offsets[m + 1]].view(p.T, p.nu)
+
+    def step(self, q0, U, seed, step, hp, m_prev, tau_cool, use_graph=True):
+        """One cycle.  hp: dict of mppi_hybrid_params fields.  U: packed per-mode
+        nominals (updated in place).  Returns dict(u, mode, tau_cool, stopped,
+        J (n,), valid (n,))."""
+        if not (U.is_cuda and U.dtype == torch.float32 and U.is_contiguous()):
+            raise TypeError("U must be a contiguous float32 CUDA tensor")
+        hpar = HybridParams(float(hp.get("lambda_switch", 0.0)), int(hp.get("cool_max", 0)),
+                            float(hp.get("v_min", 0.0)), float(hp.get("w_min", 0.0)),
+                            float(hp.get("noise_v", 0.0)), float(hp.get("noise_w", 0.0)))
+        q = (ctypes.c_float * 3)(*[float(v) for v in q0])
+        m = ctypes.c_int(int(m_prev))
+        tau = ctypes.c_int(int(tau_cool))
+        stopped = ctypes.c_int(0)
+        u = (ctypes.c_float * 3)()
+        J = np.zeros(self.n, dtype=np.float32)
+        valid = np.zeros(self.n, dtype=np.int32)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        vp = ctypes.c_void_p
+        self._check(self.lib.mppi_hybrid_step(
+            self.h, q, _ptr(U), int(seed), int(step), ctypes.byref(hpar), ctypes.byref(m),
+            ctypes.byref(tau), u, ctypes.byref(stopped), J.ctypes.data_as(vp),
+            valid.ctypes.data_as(vp), int(bool(use_graph))))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return dict(u=np.array(u[:], dtype=np.float32), mode=m.value, tau_cool=tau.value,
+                    stopped=bool(stopped.value), J=J, valid=valid.astype(bool))
 
 
 class Proposal:

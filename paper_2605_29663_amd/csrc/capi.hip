@@ -37,8 +37,8 @@ int mppi_create(mppi_ctx* out, int device, void* hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard g(device);
     e = ctx->n_valid.ensure(sizeof(int));
-    if (e == hipSuccess) e = ctx->out4.ensure(4 * sizeof(float));
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_out), 4 * sizeof(float), 0);
+    if (e == hipSuccess) e = ctx->out.ensure(OUT_FLOATS * sizeof(float));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_out), OUT_FLOATS * sizeof(float), 0);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->n_valid.p, 0, sizeof(int), ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
@@ -58,7 +58,7 @@ int mppi_destroy(mppi_ctx ctx) {
                           &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
                           &ctx->eps_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
                           &ctx->key, &ctx->key64, &ctx->unew, &ctx->nom_poses,
-                          &ctx->key_nom, &ctx->out4};
+                          &ctx->key_nom, &ctx->out};
         for (DevBuf* b : bufs) b->release();
         if (ctx->h_out) (void)hipHostFree(ctx->h_out);
         if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -326,9 +326,10 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
             return rc;
     }
     HIP_TRY(ctx, launch_finalize(A, prm->validate ? 1 : 0, ctx->key_nom.as<unsigned int>(),
-                                 ctx->unew.as<float>(), dU, ctx->out4.as<float>(), D.U_upd,
-                                 D.d_nom, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_out, ctx->out4.p, 4 * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+                                 ctx->nom_poses.as<float4>(), ctx->unew.as<float>(), dU,
+                                 ctx->out.as<float>(), D.U_upd, D.d_nom, D.J_nom, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_out, ctx->out.p, OUT_FLOATS * sizeof(float), hipMemcpyDeviceToHost,
+                                ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->prof) {
         float ms = 0.f;

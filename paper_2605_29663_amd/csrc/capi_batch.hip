@@ -16,6 +16,7 @@ struct mppi_batch_s {
     std::vector<mppi_params> prms;
     std::vector<StepArgs> args;     // static part of each scene's step arguments
     std::vector<int> u_off;         // offsets of the scenes' nominals in the packed array
+    std::vector<uint64_t> noise_stream;  // Philox stream word of each scene (0 by default)
     // snapshot of what the plan was built from
     std::vector<int> snap_n;
     std::vector<const void*> snap_ptr;
@@ -32,6 +33,24 @@ struct mppi_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool planned = false;
+    bool capturing = false;
+    // HIP-event timing of the sampled-rollout signed-distance pass (eager steps)
+    bool prof = false, prof_pending = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double prof_ms = 0.0;
+    long long prof_n = 0;
+};
+
+static_assert(HYB_MAX_MODES == MPPI_MAX_MODES, "mode capacity of the C ABI");
+
+struct mppi_hybrid_s {
+    mppi_batch b = nullptr;
+    int n = 0;
+    int model[HYB_MAX_MODES] = {};
+    int nu[HYB_MAX_MODES] = {};
+    DevBuf d_res;
+    float* h_res = nullptr;  // pinned
+    std::string err;
 };
 
 namespace {
@@ -141,7 +160,7 @@ int plan(mppi_batch b, double work_per_item) {
         }
     }
     BHIP(b, b->arena.ensure(std::max<size_t>(total, 256)));
-    BHIP(b, b->d_out.ensure(sizeof(float) * 4 * n));
+    BHIP(b, b->d_out.ensure(sizeof(float) * OUT_FLOATS * n));
     char* base = static_cast<char*>(b->arena.p);
     for (int s = 0; s < n; ++s) {
         const mppi_params& P = b->prms[s];
@@ -158,7 +177,7 @@ int plan(mppi_batch b, double work_per_item) {
         B.unew = reinterpret_cast<float*>(base + off[s * 9 + 5]);
         B.nom = reinterpret_cast<float4*>(base + off[s * 9 + 6]);
         B.key_nom = reinterpret_cast<unsigned int*>(base + off[s * 9 + 7]);
-        B.out4 = b->d_out.as<float>() + 4 * s;
+        B.out = b->d_out.as<float>() + OUT_FLOATS * s;
         B.validate = P.validate ? 1 : 0;
         const int cls = dmin_class(kind, padded);
         for (int pass = 0; pass < 2; ++pass) {
@@ -249,7 +268,11 @@ int enqueue_step(mppi_batch b) {
     BHIP(b, launch_batch_reset(b->d_counters.as<int>(), 2 * DMIN_CLASSES, b->stream));
     BHIP(b, launch_rollout_batched(ds, db, b->d_blk_roll.as<int2>(),
                                    static_cast<int>(b->blk_roll.size()), b->stream));
+    const bool timed = b->prof && !b->capturing;
+    if (timed) BHIP(b, hipEventRecord(b->ev0, b->stream));
     if (int rc = launch_dmin_pass(b, 0)) return rc;
+    if (timed) BHIP(b, hipEventRecord(b->ev1, b->stream));
+    b->prof_pending = timed;
     BHIP(b, launch_cost_batched(ds, db, b->d_blk_roll.as<int2>(),
                                 static_cast<int>(b->blk_roll.size()), b->stream));
     BHIP(b, launch_update_batched(ds, db, b->d_blk_upd.as<int2>(),
@@ -257,7 +280,7 @@ int enqueue_step(mppi_batch b) {
     BHIP(b, launch_nominal_batched(ds, db, n, b->stream));
     if (int rc = launch_dmin_pass(b, 1)) return rc;
     BHIP(b, launch_finalize_batched(ds, db, n, b->stream));
-    BHIP(b, hipMemcpyAsync(b->h_out, b->d_out.p, sizeof(float) * 4 * n, hipMemcpyDeviceToHost,
+    BHIP(b, hipMemcpyAsync(b->h_out, b->d_out.p, sizeof(float) * OUT_FLOATS * n, hipMemcpyDeviceToHost,
                            b->stream));
     return MPPI_OK;
 }
@@ -270,9 +293,59 @@ int fill_steps(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
         for (int k = 0; k < 3; ++k) S.P.q0[k] = q0[3 * s + k];
         S.P.seed = seeds[s];
         S.P.step = steps[s];
+        S.P.stream = b->noise_stream[s];
         S.U = dU + b->u_off[s];
     }
     return MPPI_OK;
+}
+
+// Enqueue one batched step (eagerly, or as a replay of the captured graph)
+// and the copy of the result records to pinned host memory; no host sync.
+int batch_launch(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
+                 const uint64_t* steps, int use_graph) {
+    if (!q0 || !dU || !seeds || !steps) return bfail(b, MPPI_E_ARG, "NULL argument");
+    if (!snapshot_matches(b))
+        return bfail(b, MPPI_E_STATE, "a scene's points or footprint changed: call mppi_batch_refresh");
+    fill_steps(b, q0, dU, seeds, steps);
+    if (use_graph) {
+        if (!b->exec) {
+            BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+            b->capturing = true;
+            const int rc = enqueue_step(b);
+            b->capturing = false;
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            BHIP(b, e);
+            b->graph = graph;
+            BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        }
+        BHIP(b, hipGraphLaunch(b->exec, b->stream));
+    } else {
+        if (int rc = enqueue_step(b)) return rc;
+    }
+    return MPPI_OK;
+}
+
+// Commands and validation flags of the last step (after the stream synced).
+void batch_collect(mppi_batch b, float* u_out, int* valid_out) {
+    if (b->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) {
+            b->prof_ms += ms;
+            b->prof_n += 1;
+        }
+        b->prof_pending = false;
+    }
+    if (!u_out) return;
+    for (int s = 0; s < b->n; ++s) {
+        for (int k = 0; k < b->prms[s].nu; ++k) u_out[3 * s + k] = b->h_out[OUT_FLOATS * s + k];
+        for (int k = b->prms[s].nu; k < 3; ++k) u_out[3 * s + k] = 0.0f;
+        if (valid_out) valid_out[s] = b->h_out[OUT_FLOATS * s + 3] != 0.0f;
+    }
 }
 
 }  // namespace
@@ -297,6 +370,7 @@ int mppi_batch_create(mppi_batch* out, const mppi_ctx* scenes, const mppi_params
     b->scenes.assign(scenes, scenes + n);
     b->prms.assign(prms, prms + n);
     b->u_off.assign(n + 1, 0);
+    b->noise_stream.assign(n, 0);
     const float zero3[3] = {0.f, 0.f, 0.f};
     for (int s = 0; s < n; ++s) {
         b->args.push_back(make_args(&prms[s], zero3, 0, 0));
@@ -313,7 +387,7 @@ int mppi_batch_create(mppi_batch* out, const mppi_ctx* scenes, const mppi_params
     if (e == hipSuccess) e = b->d_steps.ensure(sizeof(SceneStep) * n);
     if (e == hipSuccess) e = b->d_counters.ensure(sizeof(int) * 2 * DMIN_CLASSES);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_steps), sizeof(SceneStep) * n, 0);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(float) * 4 * n, 0);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(float) * OUT_FLOATS * n, 0);
     if (e != hipSuccess) {
         mppi_batch_destroy(b);
         return bfail(nullptr, MPPI_E_HIP, "batch setup: %s", hipGetErrorString(e));
@@ -341,6 +415,8 @@ int mppi_batch_destroy(mppi_batch b) {
             for (DevBuf& x : pass) x.release();
         if (b->h_steps) (void)hipHostFree(b->h_steps);
         if (b->h_out) (void)hipHostFree(b->h_out);
+        if (b->ev0) (void)hipEventDestroy(b->ev0);
+        if (b->ev1) (void)hipEventDestroy(b->ev1);
         if (b->own_stream) (void)hipStreamDestroy(b->stream);
     }
     delete b;
@@ -364,35 +440,38 @@ int mppi_batch_refresh(mppi_batch b) {
 int mppi_step_batched(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
                       const uint64_t* steps, float* u_out, int* valid_out, int use_graph) {
     if (!b) return MPPI_E_ARG;
-    if (!q0 || !dU || !seeds || !steps || !u_out) return bfail(b, MPPI_E_ARG, "NULL argument");
-    if (!snapshot_matches(b))
-        return bfail(b, MPPI_E_STATE, "a scene's points or footprint changed: call mppi_batch_refresh");
+    if (!u_out) return bfail(b, MPPI_E_ARG, "NULL argument");
     DeviceGuard g(b->device);
-    fill_steps(b, q0, dU, seeds, steps);
-    if (use_graph) {
-        if (!b->exec) {
-            BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
-            const int rc = enqueue_step(b);
-            hipGraph_t graph = nullptr;
-            const hipError_t e = hipStreamEndCapture(b->stream, &graph);
-            if (rc) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return rc;
-            }
-            BHIP(b, e);
-            b->graph = graph;
-            BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-        }
-        BHIP(b, hipGraphLaunch(b->exec, b->stream));
-    } else {
-        if (int rc = enqueue_step(b)) return rc;
-    }
+    if (int rc = batch_launch(b, q0, dU, seeds, steps, use_graph)) return rc;
     BHIP(b, hipStreamSynchronize(b->stream));
-    for (int s = 0; s < b->n; ++s) {
-        for (int k = 0; k < b->prms[s].nu; ++k) u_out[3 * s + k] = b->h_out[4 * s + k];
-        for (int k = b->prms[s].nu; k < 3; ++k) u_out[3 * s + k] = 0.0f;
-        if (valid_out) valid_out[s] = b->h_out[4 * s + 3] != 0.0f;
+    batch_collect(b, u_out, valid_out);
+    return MPPI_OK;
+}
+
+int mppi_batch_set_profiling(mppi_batch b, int enable) {
+    if (!b) return MPPI_E_ARG;
+    DeviceGuard g(b->device);
+    if (enable && !b->ev0) {
+        BHIP(b, hipEventCreate(&b->ev0));
+        BHIP(b, hipEventCreate(&b->ev1));
     }
+    b->prof = enable != 0;
+    b->prof_pending = false;
+    b->prof_ms = 0.0;
+    b->prof_n = 0;
+    return MPPI_OK;
+}
+
+int mppi_batch_get_profile(mppi_batch b, double* ms, long long* launches) {
+    if (!b || !ms || !launches) return MPPI_E_ARG;
+    *ms = b->prof_ms;
+    *launches = b->prof_n;
+    return MPPI_OK;
+}
+
+int mppi_batch_nominal_costs(mppi_batch b, float* J_out) {
+    if (!b || !J_out) return MPPI_E_ARG;
+    for (int s = 0; s < b->n; ++s) J_out[s] = b->h_out[OUT_FLOATS * s + 4];
     return MPPI_OK;
 }
 
@@ -465,6 +544,110 @@ int mppi_batch_info(mppi_batch b, long long* items_main, long long* items_valida
     if (items_main) *items_main = m;
     if (items_validation) *items_validation = v;
     if (work_per_item) *work_per_item = b->work_per_item;
+    return MPPI_OK;
+}
+
+// ------------------------------------------------------------ hybrid modes
+
+int mppi_hybrid_create(mppi_hybrid* out, mppi_ctx scene, const mppi_params* modes, int n_modes,
+                       void* hip_stream) {
+    if (!out) return bfail(nullptr, MPPI_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!scene || !modes || n_modes < 1 || n_modes > HYB_MAX_MODES)
+        return bfail(nullptr, MPPI_E_ARG, "need a context and 1..%d modes", HYB_MAX_MODES);
+    for (int m = 0; m < n_modes; ++m)
+        if (!modes[m].validate)
+            return bfail(nullptr, MPPI_E_ARG, "mode %d: hybrid selection needs validation on", m);
+    std::vector<mppi_ctx> sc(n_modes, scene);
+    mppi_batch b = nullptr;
+    if (int rc = mppi_batch_create(&b, sc.data(), modes, n_modes, hip_stream)) return rc;
+    // every mode draws its own noise: Philox stream word = mode index
+    for (int m = 0; m < n_modes; ++m) b->noise_stream[m] = static_cast<uint64_t>(m);
+    mppi_hybrid h = new mppi_hybrid_s;
+    h->b = b;
+    h->n = n_modes;
+    for (int m = 0; m < n_modes; ++m) {
+        h->model[m] = modes[m].model;
+        h->nu[m] = modes[m].nu;
+    }
+    DeviceGuard g(b->device);
+    hipError_t e = h->d_res.ensure(sizeof(float) * OUT_FLOATS);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h->h_res), sizeof(float) * OUT_FLOATS, 0);
+    if (e != hipSuccess) {
+        mppi_hybrid_destroy(h);
+        return bfail(nullptr, MPPI_E_HIP, "hybrid setup: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return MPPI_OK;
+}
+
+int mppi_hybrid_destroy(mppi_hybrid h) {
+    if (!h) return MPPI_OK;
+    if (h->b) {
+        DeviceGuard g(h->b->device);
+        if (h->b->stream) (void)hipStreamSynchronize(h->b->stream);
+        h->d_res.release();
+        if (h->h_res) (void)hipHostFree(h->h_res);
+        mppi_batch_destroy(h->b);
+    }
+    delete h;
+    return MPPI_OK;
+}
+
+const char* mppi_hybrid_last_error(mppi_hybrid h) {
+    return h ? (h->err.empty() && h->b ? h->b->err.c_str() : h->err.c_str()) : g_create_error.c_str();
+}
+
+mppi_batch mppi_hybrid_batch(mppi_hybrid h) { return h ? h->b : nullptr; }
+
+int mppi_hybrid_step(mppi_hybrid h, const float q0[3], float* dU, uint64_t seed, uint64_t step,
+                     const mppi_hybrid_params* hp, int* m_prev, int* tau_cool, float u_out[3],
+                     int* stopped, float* J_modes, int* valid_modes, int use_graph) {
+    if (!h) return MPPI_E_ARG;
+    h->err.clear();
+    auto hfail = [&](int code, const char* msg) {
+        h->err = msg;
+        return code;
+    };
+    if (!q0 || !dU || !hp || !m_prev || !tau_cool || !u_out) return hfail(MPPI_E_ARG, "NULL argument");
+    if (*m_prev < 0 || *m_prev >= h->n) return hfail(MPPI_E_ARG, "m_prev out of range");
+    if (*tau_cool < 0 || hp->cool_max < 0) return hfail(MPPI_E_ARG, "negative cooldown");
+    if (!(hp->lambda_switch >= 0.0f) || !(hp->v_min >= 0.0f) || !(hp->w_min >= 0.0f))
+        return hfail(MPPI_E_ARG, "lambda_switch, v_min and w_min must be >= 0");
+    mppi_batch b = h->b;
+    DeviceGuard g(b->device);
+    std::vector<float> q(3 * h->n);
+    std::vector<uint64_t> seeds(h->n, seed), steps(h->n, step);
+    for (int m = 0; m < h->n; ++m)
+        for (int k = 0; k < 3; ++k) q[3 * m + k] = q0[k];
+    if (int rc = batch_launch(b, q.data(), dU, seeds.data(), steps.data(), use_graph)) return rc;
+    HybridArgs a{};
+    a.n_modes = h->n;
+    a.m_prev = *m_prev;
+    a.tau_cool = *tau_cool;
+    a.cool_max = hp->cool_max;
+    a.lambda_switch = hp->lambda_switch;
+    a.v_min = hp->v_min;
+    a.w_min = hp->w_min;
+    a.noise_v = hp->noise_v;
+    a.noise_w = hp->noise_w;
+    for (int m = 0; m < h->n; ++m) {
+        a.model[m] = h->model[m];
+        a.nu[m] = h->nu[m];
+    }
+    BHIP(b, launch_hybrid_select(b->d_out.as<float>(), a, h->d_res.as<float>(), b->stream));
+    BHIP(b, hipMemcpyAsync(h->h_res, h->d_res.p, sizeof(float) * OUT_FLOATS, hipMemcpyDeviceToHost,
+                           b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    batch_collect(b, nullptr, nullptr);
+    for (int k = 0; k < 3; ++k) u_out[k] = h->h_res[k];
+    *m_prev = static_cast<int>(h->h_res[3]);
+    *tau_cool = static_cast<int>(h->h_res[4]);
+    for (int m = 0; m < h->n; ++m) {
+        if (J_modes) J_modes[m] = b->h_out[OUT_FLOATS * m + 4];
+        if (valid_modes) valid_modes[m] = b->h_out[OUT_FLOATS * m + 3] != 0.0f;
+    }
+    if (stopped) *stopped = h->h_res[5] != 0.0f;
     return MPPI_OK;
 }
 

@@ -72,7 +72,7 @@ struct mppi_ctx_s {
     bool moving = false;
     DevBuf px, py, pvx, pvy, pidx, n_valid;
     // step workspaces
-    DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom, out4;
+    DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom, out;
     float* h_out = nullptr;  // pinned
     // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
     std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
@@ -270,7 +270,9 @@ inline void choose_tiles(int kind, int padded, int npose, int n_points, int& blo
     block = npose >= 4096 ? 256 : 64;
     const int pose_blocks = std::max(1, (npose + block - 1) / block);
     const int resident = 256 * 4 * dmin_waves_per_simd(kind, padded) / (block / WAVE);
-    const int max_chunks = std::max(1, n_points / 32);
+    // a pass over few poses (the validation rollout) is bound by the serial
+    // point loop of one wave: split the points finer
+    const int max_chunks = std::max(1, n_points / (pose_blocks == 1 ? 16 : 32));
     int best_nc = 1;
     double best_eff = -1.0;
     for (int nc = 1; nc <= std::min(max_chunks, 4096); ++nc) {

@@ -8,6 +8,9 @@ namespace emppi {
 constexpr int WAVE = 64;
 constexpr int DMIN_TILE = 1024;      // points staged in LDS per tile
 constexpr int MPPI_MAX_T_DEV = 128;  // horizon capacity (MPPI_MAX_T of the C ABI)
+// Per-step result record: u*_0, u*_1, u*_2, valid, J_nom (noise-free cost of
+// the validated nominal), then padding.
+constexpr int OUT_FLOATS = 8;
 
 // Step parameters as the kernels see them (POD, passed by value).
 struct StepArgs {
@@ -109,8 +112,8 @@ hipError_t launch_nominal(const StepArgs& P, const float* Unew, float4* nom_pose
                           unsigned int* key_nom, hipStream_t s);
 
 hipError_t launch_finalize(const StepArgs& P, int validate, const unsigned int* key_nom,
-                           const float* Unew, float* U, float* out4, float* diag_unew,
-                           float* diag_dnom, hipStream_t s);
+                           const float4* nom, const float* Unew, float* U, float* out,
+                           float* diag_unew, float* diag_dnom, float* diag_jnom, hipStream_t s);
 
 // ---------------------------------------------------------------- batched path
 // Per-step arguments of one scene (refreshed by one host-to-device copy per
@@ -130,7 +133,7 @@ struct SceneBufs {
     float* unew;     // [T][nu]
     float4* nom;     // [T]
     unsigned int* key_nom;  // [T]
-    float* out4;     // 4 floats
+    float* out;      // OUT_FLOATS floats
     int validate;    // run Algorithm 1 step 4 for this scene
 };
 
@@ -171,5 +174,20 @@ hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs,
 hipError_t launch_finalize_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
                                    hipStream_t s);
 int dmin_persistent_waves(int cls);
+
+// ---------------------------------------------------------------- hybrid modes
+constexpr int HYB_MAX_MODES = 8;
+
+// Mode selection and actuator post-processing of one hybrid-mode cycle
+// (Algorithm 2, steps 2 and 3), from the per-mode result records.
+struct HybridArgs {
+    int n_modes, m_prev, tau_cool, cool_max;
+    float lambda_switch, v_min, w_min, noise_v, noise_w;
+    int model[HYB_MAX_MODES];
+    int nu[HYB_MAX_MODES];
+};
+
+// res = (u*_0, u*_1, u*_2, m*, tau_cool', safe_stop, Jbar(m*), 0).
+hipError_t launch_hybrid_select(const float* out, const HybridArgs& a, float* res, hipStream_t s);
 
 }  // namespace emppi

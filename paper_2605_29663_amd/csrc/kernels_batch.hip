@@ -19,10 +19,10 @@ __global__ void k_batch_reset(int* counters, int n) {
     if (threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_rollout_b(const SceneStep* __restrict__ steps,
+__global__ __launch_bounds__(ROLL_THREADS) void k_rollout_b(const SceneStep* __restrict__ steps,
                                                    const SceneBufs* __restrict__ bufs,
                                                    const int2* __restrict__ blk) {
-    __shared__ float lds[3 * WAVE * ROLL_HCHUNK];
+    __shared__ float lds[ROLL_LDS_FLOATS];
     const int2 b = blk[blockIdx.x];  // (scene, first rollout)
     const SceneStep& S = steps[b.x];
     const SceneBufs& B = bufs[b.x];
@@ -147,9 +147,9 @@ __global__ __launch_bounds__(256) void k_update_b(const SceneStep* __restrict__ 
     update_block(S.P, B.jt, B.eps_ws, S.U, B.unew, nullptr, b.y, sh);
 }
 
-__global__ __launch_bounds__(64) void k_nominal_b(const SceneStep* __restrict__ steps,
+__global__ __launch_bounds__(NOM_THREADS) void k_nominal_b(const SceneStep* __restrict__ steps,
                                                   const SceneBufs* __restrict__ bufs) {
-    __shared__ float lds[3 * MPPI_MAX_T_DEV];
+    __shared__ float lds[NOM_LDS_FLOATS];
     const SceneBufs& B = bufs[blockIdx.x];
     nominal_block(steps[blockIdx.x].P, B.unew, B.nom, B.key_nom, lds);
 }
@@ -158,10 +158,72 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_b(const SceneStep* __r
                                                             const SceneBufs* __restrict__ bufs) {
     const SceneStep& S = steps[blockIdx.x];
     const SceneBufs& B = bufs[blockIdx.x];
-    finalize_block(S.P, B.validate, B.key_nom, B.unew, S.U, B.out4, nullptr, nullptr);
+    __shared__ float sh[16];
+    finalize_block(S.P, B.validate, B.key_nom, B.nom, B.unew, S.U, B.out, nullptr, nullptr, nullptr,
+                   sh);
+}
+
+// Hybrid-mode selection (Algorithm 2 steps 2-3), one thread: penalised costs
+// Jbar_m = J_m + lambda_switch [m != m_prev] for validated modes (else
+// +inf); safe stop (zero command, previous mode) when no mode validated;
+// otherwise the lowest-index argmin, held at m_prev while the cooldown runs;
+// then the command of the chosen mode with the velocity / yaw-rate deadzone
+// correction.  `out` holds each mode's result record (OUT_FLOATS floats).
+__global__ void k_hybrid_select(const float* __restrict__ out, HybridArgs a, float* __restrict__ res) {
+    if (threadIdx.x != 0) return;
+    float best = INFINITY;
+    int mstar = -1;
+    for (int m = 0; m < a.n_modes; ++m) {
+        const float* o = out + m * OUT_FLOATS;
+        const float jb = o[3] != 0.0f ? o[4] + (m != a.m_prev ? a.lambda_switch : 0.0f) : INFINITY;
+        if (jb < best) {
+            best = jb;
+            mstar = m;
+        }
+    }
+    for (int k = 0; k < OUT_FLOATS; ++k) res[k] = 0.0f;
+    if (mstar < 0) {  // every mode failed validation
+        res[3] = static_cast<float>(a.m_prev);
+        res[4] = static_cast<float>(a.tau_cool);
+        res[5] = 1.0f;
+        res[6] = INFINITY;
+        return;
+    }
+    if (a.tau_cool > 0 && mstar != a.m_prev) mstar = a.m_prev;
+    const int tau = mstar != a.m_prev ? a.cool_max : max(a.tau_cool - 1, 0);
+    const float* o = out + mstar * OUT_FLOATS;
+    const int model = a.model[mstar], nu = a.nu[mstar];
+    float u[3];
+    for (int k = 0; k < 3; ++k) u[k] = k < nu ? o[k] : 0.0f;  // command structure of mode m*
+    if (model != 3) {
+        // translational modes: linear part (v) or (vx, vy) for the omni model
+        const int nlin = model == 2 ? 2 : 1;
+        float v2 = 0.0f;
+        for (int k = 0; k < nlin; ++k) v2 += u[k] * u[k];
+        const float vmag = __builtin_sqrtf(v2);
+        if (a.noise_v < vmag && vmag < a.v_min) {
+            const float sc = a.v_min / vmag;
+            for (int k = 0; k < nlin; ++k) u[k] *= sc;
+        }
+    } else {
+        // spin in place: yaw rate
+        const float w = u[0];
+        if (a.noise_w < fabsf(w) && fabsf(w) < a.w_min) u[0] = copysignf(a.w_min, w);
+    }
+    for (int k = 0; k < 3; ++k) res[k] = u[k];
+    res[3] = static_cast<float>(mstar);
+    res[4] = static_cast<float>(tau);
+    res[5] = 0.0f;
+    const float* os = out + mstar * OUT_FLOATS;
+    res[6] = os[3] != 0.0f ? os[4] + (mstar != a.m_prev ? a.lambda_switch : 0.0f) : INFINITY;
 }
 
 }  // namespace
+
+hipError_t launch_hybrid_select(const float* out, const HybridArgs& a, float* res, hipStream_t s) {
+    hipLaunchKernelGGL(k_hybrid_select, dim3(1), dim3(64), 0, s, out, a, res);
+    return hipGetLastError();
+}
 
 int dmin_persistent_waves(int cls) { return cls == 0 ? 3 : 2; }
 
@@ -173,7 +235,7 @@ hipError_t launch_batch_reset(int* counters, int n, hipStream_t s) {
 hipError_t launch_rollout_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
                                   int nblk, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rollout_b, dim3(nblk), dim3(256), 0, s, steps, bufs, blk);
+    hipLaunchKernelGGL(k_rollout_b, dim3(nblk), dim3(ROLL_THREADS), 0, s, steps, bufs, blk);
     return hipGetLastError();
 }
 
@@ -211,7 +273,7 @@ hipError_t launch_update_batched(const SceneStep* steps, const SceneBufs* bufs, 
 hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
                                   hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_nominal_b, dim3(n), dim3(WAVE), 0, s, steps, bufs);
+    hipLaunchKernelGGL(k_nominal_b, dim3(n), dim3(NOM_THREADS), 0, s, steps, bufs);
     return hipGetLastError();
 }
 

@@ -8,9 +8,9 @@ namespace emppi {
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_rollout(StepArgs P, const float* __restrict__ U,
+__global__ __launch_bounds__(ROLL_THREADS) void k_rollout(StepArgs P, const float* __restrict__ U,
                                                  RolloutOut o) {
-    __shared__ float lds[3 * WAVE * ROLL_HCHUNK];
+    __shared__ float lds[ROLL_LDS_FLOATS];
     rollout_block(P, U, o, blockIdx.x * WAVE, lds);
 }
 
@@ -34,24 +34,26 @@ __global__ __launch_bounds__(256) void k_update(StepArgs P, const float* __restr
     update_block(P, jt, eps_ws, U, Unew, diag_w, blockIdx.x, sh);
 }
 
-__global__ __launch_bounds__(64) void k_nominal(StepArgs P, const float* __restrict__ Unew,
+__global__ __launch_bounds__(NOM_THREADS) void k_nominal(StepArgs P, const float* __restrict__ Unew,
                                                 float4* __restrict__ nom,
                                                 unsigned int* __restrict__ key_nom) {
-    __shared__ float lds[3 * MPPI_MAX_T_DEV];
+    __shared__ float lds[NOM_LDS_FLOATS];
     nominal_block(P, Unew, nom, key_nom, lds);
 }
 
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(
     StepArgs P, int validate, const unsigned int* __restrict__ key_nom,
-    const float* __restrict__ Unew, float* __restrict__ U, float* __restrict__ out4,
-    float* __restrict__ diag_unew, float* __restrict__ diag_dnom) {
-    finalize_block(P, validate, key_nom, Unew, U, out4, diag_unew, diag_dnom);
+    const float4* __restrict__ nom, const float* __restrict__ Unew, float* __restrict__ U,
+    float* __restrict__ out, float* __restrict__ diag_unew, float* __restrict__ diag_dnom,
+    float* __restrict__ diag_jnom) {
+    __shared__ float sh[16];
+    finalize_block(P, validate, key_nom, nom, Unew, U, out, diag_unew, diag_dnom, diag_jnom, sh);
 }
 
 }  // namespace
 
 hipError_t launch_rollout(const StepArgs& P, const float* U, const RolloutOut& o, hipStream_t s) {
-    hipLaunchKernelGGL(k_rollout, dim3(P.Kpad / WAVE), dim3(256), 0, s, P, U, o);
+    hipLaunchKernelGGL(k_rollout, dim3(P.Kpad / WAVE), dim3(ROLL_THREADS), 0, s, P, U, o);
     return hipGetLastError();
 }
 
@@ -71,15 +73,15 @@ hipError_t launch_update(const StepArgs& P, const float* jt, const float* eps_ws
 
 hipError_t launch_nominal(const StepArgs& P, const float* Unew, float4* nom, unsigned int* key_nom,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_nominal, dim3(1), dim3(WAVE), 0, s, P, Unew, nom, key_nom);
+    hipLaunchKernelGGL(k_nominal, dim3(1), dim3(NOM_THREADS), 0, s, P, Unew, nom, key_nom);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const StepArgs& P, int validate, const unsigned int* key_nom,
-                           const float* Unew, float* U, float* out4, float* diag_unew,
-                           float* diag_dnom, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, P, validate, key_nom, Unew, U,
-                       out4, diag_unew, diag_dnom);
+                           const float4* nom, const float* Unew, float* U, float* out,
+                           float* diag_unew, float* diag_dnom, float* diag_jnom, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, P, validate, key_nom, nom, Unew,
+                       U, out, diag_unew, diag_dnom, diag_jnom);
     return hipGetLastError();
 }
 

@@ -9,40 +9,56 @@
 
 namespace emppi {
 
-constexpr int ROLL_HCHUNK = 16;    // horizon steps of controls staged in LDS per chunk
-constexpr int COST_THREADS = 1024; // 64 rollouts x 16 horizon groups
-constexpr int FIN_THREADS = 128;   // one thread per horizon step
+constexpr int ROLL_HCHUNK = 16;                   // horizon steps per rollout chunk
+constexpr int ROLL_THREADS = WAVE * ROLL_HCHUNK;  // one (rollout, step) pair per thread
+constexpr int ROLL_LDS_FLOATS = 6 * WAVE * ROLL_HCHUNK;  // controls, headings, (cos, sin)
+constexpr int COST_THREADS = 1024;  // 64 rollouts x 16 horizon groups
+constexpr int FIN_THREADS = 128;    // one thread per horizon step
+constexpr int NOM_THREADS = 128;    // one thread per horizon step
+constexpr int NOM_LDS_FLOATS = 6 * MPPI_MAX_T_DEV;
 
 // One forward-Euler step q_{h+1} = q_h + F_m(q_h, u_h) dt (Section "Robot
-// Kinematic Models") in the fixed single-precision sequence; (s, c) =
-// sin/cos of theta_h.  "a += b dt" is one fma(b, dt, a).
-__device__ __forceinline__ void euler_step(int model, const float u[3], float dt, float L, float s,
-                                           float c, float& x, float& y, float& th) {
+// Kinematic Models") in the fixed single-precision sequence, split into the
+// heading recursion theta_{h+1} = theta_h + omega(u_h) dt (which does not
+// depend on the position) and the position update, which uses (s, c) = sin /
+// cos of theta_h.  "a += b dt" is one fma(b, dt, a).  Splitting the two lets
+// the costly sin/cos and tan of every step run in parallel while the serial
+// recursions are single fma chains; the values are the same as a plain
+// step-by-step integration.
+__device__ __forceinline__ bool model_rotates(int model) { return model <= 3; }
+
+__device__ __forceinline__ float heading_rate(int model, const float u[3], float L) {
     switch (model) {
-    case 0:  // unicycle (v, omega)
-        x = __builtin_fmaf(u[0] * c, dt, x);
-        y = __builtin_fmaf(u[0] * s, dt, y);
-        th = __builtin_fmaf(u[1], dt, th);
-        break;
-    case 1: {  // Ackermann (v, delta): theta' = v tan(delta) / L
-        const float w = (u[0] * seq_tan(u[1])) / L;
-        x = __builtin_fmaf(u[0] * c, dt, x);
-        y = __builtin_fmaf(u[0] * s, dt, y);
-        th = __builtin_fmaf(w, dt, th);
-        break;
+    case 0: return u[1];                        // unicycle (v, omega)
+    case 1: return (u[0] * seq_tan(u[1])) / L;  // Ackermann (v, delta): v tan(delta) / L
+    case 2: return u[2];                        // omni (vx, vy, omega)
+    case 3: return u[0];                        // spin in place (omega)
+    default: return 0.0f;                       // parallel: heading held
     }
-    case 2: {  // omni (vx, vy, omega)
+}
+
+__device__ __forceinline__ float heading_step(int model, float w, float dt, float th) {
+    return model_rotates(model) ? __builtin_fmaf(w, dt, th) : th;
+}
+
+__device__ __forceinline__ void position_step(int model, const float u[3], float dt, float s,
+                                              float c, float& x, float& y) {
+    switch (model) {
+    case 0:
+    case 1:
+        x = __builtin_fmaf(u[0] * c, dt, x);
+        y = __builtin_fmaf(u[0] * s, dt, y);
+        break;
+    case 2: {
         const float xd = __builtin_fmaf(u[0], c, -(u[1] * s));
         const float yd = __builtin_fmaf(u[0], s, u[1] * c);
         x = __builtin_fmaf(xd, dt, x);
         y = __builtin_fmaf(yd, dt, y);
-        th = __builtin_fmaf(u[2], dt, th);
         break;
     }
-    case 3:  // spin in place (omega)
-        th = __builtin_fmaf(u[0], dt, th);
+    case 3:
         break;
-    default:  // parallel (v_para)
+    default:  // parallel (v_para): translation along the body y axis
         x = __builtin_fmaf(-(u[0] * s), dt, x);
         y = __builtin_fmaf(u[0] * c, dt, y);
         break;
@@ -58,54 +74,80 @@ __device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py
     return v;
 }
 
-// Sampling + rollouts of rollouts [r0, r0 + 64) (Algorithm 1 step 1).  For
-// each chunk of horizon steps, the whole workgroup draws the noise of the
-// 64 x chunk (r, h) pairs in parallel (sampled controls go to LDS), then one
-// wave integrates the 64 rollouts through the chunk.  lds: 3 * 64 *
-// ROLL_HCHUNK floats.
+// Sampling + rollouts of rollouts [r0, r0 + 64) (Algorithm 1 step 1), by
+// chunks of ROLL_HCHUNK horizon steps with ROLL_THREADS threads:
+//   (a) thread (step hh, rollout l) draws the noise of its pair, clamps the
+//       sampled control (kept in LDS) and evaluates its heading rate;
+//   (b) wave 0, lane = rollout: the heading recursion (one fma per step);
+//   (c) every thread: sin / cos of its pair's new heading;
+//   (d) wave 0: the position recursion, the scored poses, the distance keys'
+//       initial values and the task + control costs.
+// lds: ROLL_LDS_FLOATS floats.
 __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __restrict__ U,
                                               const RolloutOut& o, int r0, float* lds) {
     const int T = P.T, nu = P.nu, Kpad = P.Kpad;
-    const int r = r0 + static_cast<int>(threadIdx.x);
-    const bool live = threadIdx.x < WAVE && r < P.K;
+    float* su = lds;                               // [hh][k][lane] sampled controls
+    float* sw = lds + 3 * WAVE * ROLL_HCHUNK;      // [hh][lane] heading rate, then heading
+    float2* scs = reinterpret_cast<float2*>(lds + 4 * WAVE * ROLL_HCHUNK);  // [hh][lane] (c, s)
+    const int lane = threadIdx.x & (WAVE - 1), hh = threadIdx.x / WAVE;
+    const int r = r0 + lane;
+    const bool chain = threadIdx.x < WAVE;
     float x = P.q0[0], y = P.q0[1], th = P.q0[2], s = 0.f, c = 1.f, jb = 0.0f;
-    if (threadIdx.x < WAVE) seq_sincos(th, s, c);
+    if (chain) seq_sincos(th, s, c);
     for (int h0 = 0; h0 < T; h0 += ROLL_HCHUNK) {
         const int hn = min(ROLL_HCHUNK, T - h0);
-        for (int p = threadIdx.x; p < WAVE * hn; p += blockDim.x) {
-            const int rl = p & (WAVE - 1), hh = p / WAVE, h = h0 + hh, rr = r0 + rl;
-            if (rr >= P.K) continue;
-            float z[4];
-            normals4(P.seed, P.step, static_cast<uint32_t>(rr), static_cast<uint32_t>(h), P.stream, z);
-            for (int k = 0; k < nu; ++k) {
-                const float base = U[h * nu + k];
-                float v = base + P.sigma[k] * z[k];
-                v = fmaxf(v, P.umin[k]);
-                v = fminf(v, P.umax[k]);
-                const float e = v - base;
-                lds[(hh * 3 + k) * WAVE + rl] = v;
-                o.eps_ws[(h * nu + k) * Kpad + rr] = e;
-                const size_t d = (static_cast<size_t>(rr) * T + h) * nu + k;
-                if (o.diag_eps) o.diag_eps[d] = e;
-                if (o.diag_u) o.diag_u[d] = v;
+        const int h = h0 + hh;
+        if (hh < hn) {
+            float u[3] = {0.f, 0.f, 0.f};
+            if (r < P.K) {
+                float z[4];
+                normals4(P.seed, P.step, static_cast<uint32_t>(r), static_cast<uint32_t>(h), P.stream, z);
+                for (int k = 0; k < nu; ++k) {
+                    const float base = U[h * nu + k];
+                    float v = base + P.sigma[k] * z[k];
+                    v = fmaxf(v, P.umin[k]);
+                    v = fminf(v, P.umax[k]);
+                    const float e = v - base;
+                    u[k] = v;
+                    o.eps_ws[(h * nu + k) * Kpad + r] = e;
+                    const size_t d = (static_cast<size_t>(r) * T + h) * nu + k;
+                    if (o.diag_eps) o.diag_eps[d] = e;
+                    if (o.diag_u) o.diag_u[d] = v;
+                }
+            }
+            for (int k = 0; k < 3; ++k) su[(hh * 3 + k) * WAVE + lane] = u[k];
+            sw[hh * WAVE + lane] = heading_rate(P.model, u, P.wheelbase);
+        }
+        __syncthreads();
+        if (chain) {
+            for (int k = 0; k < hn; ++k) {
+                th = heading_step(P.model, sw[k * WAVE + lane], P.dt, th);
+                sw[k * WAVE + lane] = th;
             }
         }
         __syncthreads();
-        if (threadIdx.x < WAVE) {
-            for (int hh = 0; hh < hn; ++hh) {
-                const int h = h0 + hh;
-                float u[3] = {0.f, 0.f, 0.f};
-                if (live)
-                    for (int k = 0; k < nu; ++k) u[k] = lds[(hh * 3 + k) * WAVE + threadIdx.x];
+        if (hh < hn) {
+            float sn, cn;
+            seq_sincos(sw[hh * WAVE + lane], sn, cn);
+            scs[hh * WAVE + lane] = make_float2(cn, sn);
+        }
+        __syncthreads();
+        if (chain) {
+            for (int k = 0; k < hn; ++k) {
+                const int hk = h0 + k;
+                float u[3];
+                for (int q = 0; q < 3; ++q) u[q] = su[(k * 3 + q) * WAVE + lane];
                 float4 pose = make_float4(x, y, c, s);
-                euler_step(P.model, u, P.dt, P.wheelbase, s, c, x, y, th);
-                seq_sincos(th, s, c);
+                position_step(P.model, u, P.dt, s, c, x, y);
+                const float2 cs = scs[k * WAVE + lane];
+                c = cs.x;
+                s = cs.y;
                 if (P.state_offset) pose = make_float4(x, y, c, s);
-                o.poses[h * Kpad + r] = pose;
-                if (o.key) o.key[h * Kpad + r] = DKEY_INIT;
-                if (o.key64) o.key64[h * Kpad + r] = DKEY64_INIT;
-                if (o.diag_poses && live) {
-                    float* dp = o.diag_poses + (static_cast<size_t>(r) * T + h) * 4;
+                o.poses[hk * Kpad + r] = pose;
+                if (o.key) o.key[hk * Kpad + r] = DKEY_INIT;
+                if (o.key64) o.key64[hk * Kpad + r] = DKEY64_INIT;
+                if (o.diag_poses && r < P.K) {
+                    float* dp = o.diag_poses + (static_cast<size_t>(r) * T + hk) * 4;
                     dp[0] = pose.x;
                     dp[1] = pose.y;
                     dp[2] = pose.z;
@@ -116,7 +158,7 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
         }
         __syncthreads();
     }
-    if (threadIdx.x < WAVE) o.jbase[r] = jb;
+    if (chain) o.jbase[r] = jb;
 }
 
 // J~ of rollouts [r0, r0 + 64) (Algorithm 1 steps 2-3): lane l, group q of
@@ -224,48 +266,86 @@ __device__ __forceinline__ void update_block(const StepArgs& P, const float* __r
 }
 
 // Nominal trajectory of the updated sequence (Algorithm 1 step 4) in the same
-// single-precision sequence as the sampled rollouts.  The sequence is first
-// copied to LDS (lds: 3 * MPPI_MAX_T floats), then lane 0 integrates; the
-// distance keys of the T nominal poses are initialised on the way.
+// single-precision sequence as the sampled rollouts, with NOM_THREADS threads
+// (thread h = horizon step h): heading rates in parallel, the heading
+// recursion on thread 0, sin / cos in parallel, the position recursion on
+// thread 0.  The distance keys of the T nominal poses are initialised on the
+// way.  lds: NOM_LDS_FLOATS floats.
 __device__ __forceinline__ void nominal_block(const StepArgs& P, const float* __restrict__ Unew,
                                               float4* __restrict__ nom,
                                               unsigned int* __restrict__ key_nom, float* lds) {
-    for (int k = threadIdx.x; k < P.T * P.nu; k += blockDim.x) lds[k] = Unew[k];
-    for (int h = threadIdx.x; h < P.T; h += blockDim.x) key_nom[h] = DKEY_INIT;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    float x = P.q0[0], y = P.q0[1], th = P.q0[2], s, c;
-    seq_sincos(th, s, c);
-    for (int h = 0; h < P.T; ++h) {
+    const int T = P.T, nu = P.nu, h = threadIdx.x;
+    float* su = lds;                          // [h][3]
+    float* sw = lds + 3 * MPPI_MAX_T_DEV;     // heading rate, then heading after step h
+    float2* scs = reinterpret_cast<float2*>(lds + 4 * MPPI_MAX_T_DEV);
+    if (h < T) {
         float u[3] = {0.f, 0.f, 0.f};
-        for (int k = 0; k < P.nu; ++k) u[k] = lds[h * P.nu + k];
+        for (int k = 0; k < nu; ++k) u[k] = Unew[h * nu + k];
+        for (int k = 0; k < 3; ++k) su[h * 3 + k] = u[k];
+        sw[h] = heading_rate(P.model, u, P.wheelbase);
+        key_nom[h] = DKEY_INIT;
+    }
+    __syncthreads();
+    if (h == 0) {
+        float th = P.q0[2];
+        for (int k = 0; k < T; ++k) {
+            th = heading_step(P.model, sw[k], P.dt, th);
+            sw[k] = th;
+        }
+    }
+    __syncthreads();
+    if (h < T) {
+        float sn, cn;
+        seq_sincos(sw[h], sn, cn);
+        scs[h] = make_float2(cn, sn);
+    }
+    __syncthreads();
+    if (h != 0) return;
+    float x = P.q0[0], y = P.q0[1], s, c;
+    seq_sincos(P.q0[2], s, c);
+    for (int k = 0; k < T; ++k) {
+        const float u[3] = {su[k * 3], su[k * 3 + 1], su[k * 3 + 2]};
         float4 pose = make_float4(x, y, c, s);
-        euler_step(P.model, u, P.dt, P.wheelbase, s, c, x, y, th);
-        seq_sincos(th, s, c);
+        position_step(P.model, u, P.dt, s, c, x, y);
+        const float2 cs = scs[k];
+        c = cs.x;
+        s = cs.y;
         if (P.state_offset) pose = make_float4(x, y, c, s);
-        nom[h] = pose;
+        nom[k] = pose;
     }
 }
 
 // Validation and execution (Algorithm 1 step 4): valid iff every
 // d_nom >= d_safe; then u* = U_0 and U shifts left (last entry repeated),
-// else u* = 0 and U = 0.  out4 = (u*_0, u*_1, u*_2, valid).  One thread per
-// horizon step (MPPI_MAX_T_DEV threads).
+// else u* = 0 and U = 0.  The noise-free cost of the updated nominal, J_nom =
+// sum_h [phi_task + phi_ctrl + phi_obs] along the validation rollout (+ w_inf
+// if unsafe), is what the hybrid-mode selection compares across modes.
+// out = (u*_0, u*_1, u*_2, valid, J_nom, 0, 0, 0).  One thread per horizon
+// step (FIN_THREADS threads); sh: 16 floats.
 __device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
                                                const unsigned int* __restrict__ key_nom,
+                                               const float4* __restrict__ nom,
                                                const float* __restrict__ Unew,
-                                               float* __restrict__ U, float* __restrict__ out4,
+                                               float* __restrict__ U, float* __restrict__ out,
                                                float* __restrict__ diag_unew,
-                                               float* __restrict__ diag_dnom) {
+                                               float* __restrict__ diag_dnom,
+                                               float* __restrict__ diag_jnom, float* sh) {
     const int T = P.T, nu = P.nu, h = threadIdx.x;
     int bad = 0;
+    float term = 0.0f;
     if (validate && h < T) {
         const float sq = dkey_value(key_nom[h]);
         const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
         bad = !(d >= P.d_safe);
         if (diag_dnom) diag_dnom[h] = d;
+        float u[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < nu; ++k) u[k] = Unew[h * nu + k];
+        const float4 p = nom[h];
+        const float gap = fmaxf(P.d_safe - d, 0.0f);
+        term = task_ctrl(P, p.x, p.y, u) + ((d < 0.0f ? P.w_coll : 0.0f) + P.w_rep * (gap * gap));
     }
     const int ok = !__syncthreads_or(bad);
+    const float jsum = block_reduce(term, sh, [](float a, float c) { return a + c; });
     if (h < T) {
         const int src = (h + 1 < T ? h + 1 : T - 1) * nu;
         for (int k = 0; k < nu; ++k) {
@@ -274,8 +354,12 @@ __device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
         }
     }
     if (h == 0) {
-        for (int k = 0; k < 3; ++k) out4[k] = (ok && k < nu) ? Unew[k] : 0.0f;
-        out4[3] = ok ? 1.0f : 0.0f;
+        const float jn = validate ? jsum + (ok ? 0.0f : P.w_inf) : NAN;
+        for (int k = 0; k < 3; ++k) out[k] = (ok && k < nu) ? Unew[k] : 0.0f;
+        out[3] = ok ? 1.0f : 0.0f;
+        out[4] = jn;
+        for (int k = 5; k < OUT_FLOATS; ++k) out[k] = 0.0f;
+        if (diag_jnom) diag_jnom[0] = jn;
     }
 }
 

@@ -119,6 +119,27 @@ def params(name, **over):
     return q
 
 
+# Hybrid-mode platform (Section "Extension to Hybrid-Mode Platforms"; the
+# command limits of the Ranger-mini modes of the platform table): a 0.74 x
+# 0.50 m body with a 0.27 x 0.2 m side attachment; dual-Ackermann (v, delta)
+# with the effective wheelbase = half the 0.5 m axle distance, parallel
+# motion (v_para, the lateral-translation model) and spin in place (omega).
+FOOTPRINT_RANGER6 = np.array([(-0.37, -0.25), (0.37, -0.25), (0.37, 0.25), (0.10, 0.25),
+                              (0.10, 0.45), (-0.37, 0.45)], dtype=np.float64)
+
+
+def hybrid_modes(K=1024, T=40, dt=0.05, goal=(3.0, 0.0), **over):
+    """Parameter sets of the three Ranger-mini modes (dual-Ackermann, parallel, spin)."""
+    base = dict(COST_DEFAULTS, K=K, T=T, dt=dt, footprint_kind=0, goal=goal, wheelbase=0.25)
+    modes = [dict(base, model="ackermann", nu=2, sigma=(0.5, 0.3), u_min=(-1.5, -0.6),
+                  u_max=(1.5, 0.6)),
+             dict(base, model="parallel", nu=1, sigma=(0.3,), u_min=(-0.6,), u_max=(0.6,)),
+             dict(base, model="spin", nu=1, sigma=(0.5,), u_min=(-1.0,), u_max=(1.0,))]
+    for m in modes:
+        m.update(over)
+    return modes
+
+
 CONFIG_DOC = {
     "c1": "unicycle dt=0.1 K=256 T=20, L8 footprint (B=8), N=512 uniform in [-3,3]^2",
     "c2": "ackermann L=1 dt=0.05 K=2048 T=40, towed16 footprint (B=16), N=8192 corridor",

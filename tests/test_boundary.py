@@ -49,7 +49,10 @@ def test_params_struct_layout_matches_header():
     import paper_2605_29663_amd as pkg
     assert ctypes.sizeof(pkg.MppiParams) == 4 * (5 + 3 + 9 + 5 + 3 + 2 + 2)
     assert pkg.MppiParams.goal.offset == 4 * (5 + 3 + 9 + 5 + 3)
-    assert ctypes.sizeof(pkg.MppiDiag) == 9 * 8
+    assert ctypes.sizeof(pkg.MppiDiag) == 10 * 8
+    # mppi_hybrid_params: float, int32, 4 floats
+    assert ctypes.sizeof(pkg.HybridParams) == 6 * 4
+    assert pkg.HybridParams.v_min.offset == 8
 
 
 @pytest.mark.parametrize("poly,code", [

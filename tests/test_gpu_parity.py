@@ -263,6 +263,11 @@ def _check_step_rows(orc, prm, sc, q0, U0, seed, step, u_star, valid, D, U_after
             assert valid == orc.validate_shift(U_upd, dn_o, prm["d_safe"])[0]
         np.testing.assert_array_equal(u_star, np.float32(us_o))
         np.testing.assert_array_equal(_np(U_after), np.float32(Un_o))
+        # noise-free cost of the updated nominal, from the GPU's nominal and d_nom
+        Jn_o = orc.costs(prm, nom[None, :, :2], U_upd[None], dn[None])[2][0]
+        np.testing.assert_allclose(float(_np(D["J_nom"])[0]), Jn_o, rtol=1e-5, atol=1e-5)
+    else:
+        assert np.isnan(_np(D["J_nom"])[0])
     return Jt
 
 
