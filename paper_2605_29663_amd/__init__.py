@@ -87,6 +87,9 @@ def load():
                            "`python -m paper_2605_29663_amd.build` (no CPU fallback exists)")
     L = ctypes.CDLL(LIB_PATH)
     vp, i, f, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_uint64
+    # every entry point returns an int status unless set otherwise below
+    for name in EXPORTS:
+        getattr(L, name).restype = i
     L.mppi_create.argtypes = [ctypes.POINTER(vp), i, vp]
     L.mppi_destroy.argtypes = [vp]
     L.mppi_last_error.argtypes = [vp]
@@ -151,11 +154,6 @@ def load():
     L.proposal_get_buffer.argtypes = [vp, i, vp, ll]
     L.proposal_save.argtypes = [vp, ctypes.c_char_p]
     L.proposal_load.argtypes = [vp, ctypes.c_char_p]
-    for name in EXPORTS:
-        if name in ("proposal_num_params",):
-            continue
-        if name not in ("mppi_last_error", "mppi_batch_last_error", "proposal_last_error"):
-            getattr(L, name).restype = i
     _lib = L
     return L
 

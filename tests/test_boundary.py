@@ -36,6 +36,29 @@ def test_header_declares_entry_points():
         assert n in names
 
 
+def _declared_returns():
+    """(return type text, name) of every declaration."""
+    out = []
+    for h in HEADERS:
+        txt = open(h).read()
+        out += re.findall(r"MPPI_API\s+([\w\s\*]+?)\s*\b(\w+)\s*\(", txt)
+    return [(" ".join(r.split()), n) for r, n in out]
+
+
+def test_binding_return_types_match_header():
+    """A pointer returned through a 32-bit int would be truncated: the ctypes
+    return type of every binding must match the header's."""
+    pkg, L = _lib()
+    want = {"int": ctypes.c_int, "const char*": ctypes.c_char_p, "const char *": ctypes.c_char_p,
+            "long long": ctypes.c_longlong, "mppi_batch": ctypes.c_void_p}
+    for ret, name in _declared_returns():
+        if name not in pkg.EXPORTS:
+            continue
+        assert ret in want, (ret, name)
+        assert getattr(L, name).restype is want[ret], (name, ret, getattr(L, name).restype)
+    assert set(pkg.EXPORTS) == set(n for _, n in _declared_returns())
+
+
 def test_library_exports_every_declared_symbol():
     pkg, L = _lib()
     for n in _declared():
