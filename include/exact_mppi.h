@@ -54,6 +54,7 @@ enum { MPPI_UNICYCLE = 0, MPPI_ACKERMANN = 1, MPPI_OMNI = 2, MPPI_SPIN = 3, MPPI
 #define MPPI_MAX_R 32        /* rectangles in a cover */
 #define MPPI_MAX_T 128       /* horizon */
 #define MPPI_MAX_K (1 << 20) /* rollouts */
+#define MPPI_MAX_PATH 64     /* guidance waypoints */
 
 typedef struct mppi_ctx_s* mppi_ctx;
 
@@ -72,6 +73,9 @@ typedef struct mppi_ctx_s* mppi_ctx;
  *                     augmented cost (Section "Safety Penalties and
  *                     Trajectory Validation")
  *   w_goal, goal[2]   task term w_goal * |(x, y) - goal|
+ *   w_path            path-following task term w_path * (distance of (x, y)
+ *                     to the guidance polyline set by set_guidance; no term
+ *                     while no guidance is set)
  *   w_ctrl[c]         control term sum_c w_ctrl[c] u_c^2
  *   state_offset      1: the (r, h) term scores the post-step state q_{h+1}
  *                     (moving points at time (h+1) dt); 0: the pre-step q_h
@@ -86,7 +90,45 @@ typedef struct mppi_params {
     float goal[2];
     int32_t state_offset;
     int32_t validate;
+    float w_path;
 } mppi_params;
+
+/* Weak guidance (Section "Problem Statement": a waypoint sequence from an
+ * upstream module; the task term's "path following"): host array of n
+ * planning-frame waypoints (x0, y0, x1, y1, ...), copied synchronously into
+ * the context.  The task term adds w_path * min over the polyline's segments
+ * of the point-segment distance (one waypoint: the distance to it).
+ * 0 <= n <= MPPI_MAX_PATH; n = 0 removes the guidance.  Non-finite values:
+ * MPPI_E_ARG.  Takes effect from the next step, in batches too.             */
+MPPI_API int set_guidance(mppi_ctx ctx, const float* host_xy, int n);
+
+/* Point-cloud pre-processing (Section "Problem Statement": the obstacle set
+ * is the local point cloud restricted to a task-relevant height band and
+ * downsampled to a fixed budget N before rollout evaluation; the paper does
+ * not name the downsampling method).  Reading implemented:
+ *   a point (x, y, z) is kept if it is finite, z_min <= z <= z_max and its
+ *   single-precision squared planar range to center, (x-cx)^2 + (y-cy)^2,
+ *   is <= r_max^2; its voxel is (floor(x / voxel), floor(y / voxel));
+ *   each occupied voxel is represented by its kept point of lowest index;
+ *   if more than n_out voxels are occupied, the n_out representatives of
+ *   smallest (squared range, index) are kept; the kept points are written in
+ *   ascending input order, the remaining slots up to n_out get valid = 0
+ *   (x = y = 0).
+ * dxyz: device m x 3 floats (row-major x, y, z, planning frame).  dx, dy,
+ * dvalid: device outputs of n_out entries, ready for set_points.  n_kept:
+ * host, may be NULL (non-NULL makes the call synchronous).  Deterministic.
+ * Limits: 0 <= m <= MPPI_MAX_CLOUD, 0 <= n_out <= MPPI_MAX_CLOUD, voxel > 0,
+ * r_max > 0, z_min <= z_max, all finite, and (max(|cx|, |cy|) + r_max) /
+ * voxel < 2^29; otherwise MPPI_E_ARG.  Workspace: about 40 bytes per input
+ * point, kept by the context.                                              */
+#define MPPI_MAX_CLOUD (1 << 20)
+typedef struct mppi_cloud_params {
+    float z_min, z_max, r_max, voxel;
+    int32_t n_out;
+} mppi_cloud_params;
+MPPI_API int cloud_downsample(mppi_ctx ctx, const float* dxyz, int m, const float center[2],
+                              const mppi_cloud_params* cp, float* dx, float* dy,
+                              unsigned char* dvalid, int* n_kept);
 
 /* Optional device outputs of mppi_step; any pointer may be NULL.
  *   d_min   K*T, row-major [r][h]: minimum signed distance over points

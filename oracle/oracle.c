@@ -225,6 +225,9 @@ EXPORT void orc_rollout_f64(int model, int T, int nu, double dt, double L,
 typedef struct {
     double d_safe, w_coll, w_rep, w_inf, w_goal, goal_x, goal_y, lambda;
     double w_ctrl[3];
+    double w_path;
+    int n_path;            /* guidance waypoints (0: no path term)          */
+    const double* path;    /* x0, y0, x1, y1, ... (planning frame)          */
 } orc_cost_params;
 
 /* Obstacle penalty phi_obs(d) = w_coll I(d < 0) + w_rep max(d_safe - d, 0)^2. */
@@ -234,11 +237,29 @@ EXPORT double orc_phi_obs(const orc_cost_params* p, double d) {
     return (d < 0.0 ? p->w_coll : 0.0) + p->w_rep * gap * gap;
 }
 
+/* Distance of (x, y) to the guidance polyline: the smallest distance to one
+ * of its segments (one waypoint: the distance to that point).              */
+EXPORT double orc_path_dist(const double* path, int n, double x, double y) {
+    double best = hypot(x - path[0], y - path[1]);
+    for (int k = 1; k < n; ++k) {
+        const double* a = path + 2 * k - 2;
+        /* a repeated waypoint is a point, not a segment */
+        double d = (a[0] == a[2] && a[1] == a[3]) ? hypot(x - a[2], y - a[3])
+                                                   : orc_seg_dist(x, y, a[0], a[1], a[2], a[3]);
+        if (d < best) best = d;
+    }
+    return best;
+}
+
 /* Task term: distance of the scored position to the goal, weighted by w_goal
- * (the paper only names "goal seeking"; this is the position-goal reading). */
+ * (the paper names "goal seeking" and "path following"; these are the
+ * position-goal reading and the distance to the guidance polyline, weighted
+ * by w_path).                                                               */
 EXPORT double orc_phi_task(const orc_cost_params* p, double x, double y) {
     double dx = x - p->goal_x, dy = y - p->goal_y;
-    return p->w_goal * sqrt(dx * dx + dy * dy);
+    double v = p->w_goal * sqrt(dx * dx + dy * dy);
+    if (p->n_path > 0) v += p->w_path * orc_path_dist(p->path, p->n_path, x, y);
+    return v;
 }
 
 /* Control regulariser: sum_c w_ctrl[c] u_c^2 of the sampled control.        */

@@ -30,7 +30,7 @@ POLYGON, RECTS = 0, 1
 
 PARAM_KEYS = ("K", "T", "nu", "model", "footprint_kind", "dt", "lambda_", "wheelbase",
               "sigma", "u_min", "u_max", "d_safe", "w_coll", "w_rep", "w_inf", "w_goal",
-              "w_ctrl", "goal", "state_offset", "validate")
+              "w_ctrl", "goal", "state_offset", "validate", "w_path", "path")
 
 
 def build() -> str:
@@ -68,6 +68,8 @@ def lib():
         L.orc_rollout_f64.argtypes = [i, i, i, d, d, vp, vp, vp]
         L.orc_phi_obs.restype = d
         L.orc_phi_obs.argtypes = [vp, d]
+        L.orc_phi_task.restype = d
+        L.orc_phi_task.argtypes = [vp, d, d]
         L.orc_costs.argtypes = [vp, i, i, i, vp, vp, vp, vp, vp, vp]
         L.orc_weights.argtypes = [i, vp, d, vp]
         L.orc_update.argtypes = [i, i, i, vp, vp, vp]
@@ -257,7 +259,8 @@ class _CostParams(ctypes.Structure):
                 ("w_rep", ctypes.c_double), ("w_inf", ctypes.c_double),
                 ("w_goal", ctypes.c_double), ("goal_x", ctypes.c_double),
                 ("goal_y", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("w_ctrl", ctypes.c_double * 3)]
+                ("w_ctrl", ctypes.c_double * 3), ("w_path", ctypes.c_double),
+                ("n_path", ctypes.c_int), ("path", ctypes.c_void_p)]
 
 
 def _cost_params(prm):
@@ -269,7 +272,20 @@ def _cost_params(prm):
     wc = _vec3(prm["w_ctrl"])
     for c in range(3):
         cp.w_ctrl[c] = float(wc[c])
+    path = prm.get("path")
+    if path is not None and len(path):
+        # the waypoints go through float32 like every other GPU input
+        pa = np.ascontiguousarray(np.asarray(path, dtype=np.float32).astype(np.float64).reshape(-1))
+        cp.w_path = f(prm.get("w_path", 0.0))
+        cp.n_path = pa.size // 2
+        cp.path = pa.ctypes.data
+        cp._keep = pa
     return cp
+
+
+def phi_task(prm, x, y):
+    cp = _cost_params(prm)
+    return lib().orc_phi_task(ctypes.byref(cp), float(x), float(y))
 
 
 def phi_obs(prm, d):

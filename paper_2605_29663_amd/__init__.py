@@ -25,7 +25,7 @@ POLYGON, RECTS = 0, 1
 MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
-           "set_footprint", "set_points",
+           "set_footprint", "set_points", "set_guidance",
            "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
            "mppi_autotune", "mppi_tune_get", "mppi_tune_set", "mppi_set_tiles",
            "mppi_set_profiling", "mppi_get_profile",
@@ -56,7 +56,7 @@ class MppiParams(ctypes.Structure):
                 ("w_coll", ctypes.c_float), ("w_rep", ctypes.c_float), ("w_inf", ctypes.c_float),
                 ("w_goal", ctypes.c_float), ("w_ctrl", ctypes.c_float * 3),
                 ("goal", ctypes.c_float * 2), ("state_offset", ctypes.c_int32),
-                ("validate", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("w_path", ctypes.c_float)]
 
 
 class HybridParams(ctypes.Structure):
@@ -97,6 +97,7 @@ def load():
     L.mppi_check_footprint.argtypes = [i, vp, i, ctypes.c_char_p, i]
     L.set_footprint.argtypes = [vp, i, vp, i]
     L.set_points.argtypes = [vp, vp, vp, vp, vp, vp, i]
+    L.set_guidance.argtypes = [vp, vp, i]
     L.sdf_polygon.argtypes = [vp, vp, vp, i, vp]
     L.sdf_rectcover.argtypes = [vp, vp, vp, i, vp]
     L.sdf_min_poses.argtypes = [vp, vp, i, i, f, i, i, vp, vp]
@@ -185,6 +186,7 @@ def make_params(p) -> MppiParams:
     m.goal[0], m.goal[1] = float(p["goal"][0]), float(p["goal"][1])
     m.state_offset = int(p["state_offset"])
     m.validate = int(p.get("validate", 1))
+    m.w_path = float(p.get("w_path", 0.0))
     return m
 
 
@@ -230,6 +232,14 @@ class Context:
             raise MppiError(rc, self.lib.mppi_last_error(self.h).decode())
 
     # ------------------------------------------------------------------ API
+    def set_guidance(self, waypoints):
+        """Guidance polyline (n, 2) in the planning frame; None or empty clears it."""
+        if waypoints is None or len(waypoints) == 0:
+            self._check(self.lib.set_guidance(self.h, None, 0))
+            return
+        a = np.ascontiguousarray(np.asarray(waypoints, dtype=np.float32).reshape(-1, 2))
+        self._check(self.lib.set_guidance(self.h, a.ctypes.data_as(ctypes.c_void_p), a.shape[0]))
+
     def set_footprint(self, kind, data):
         a = np.ascontiguousarray(np.asarray(data, dtype=np.float32))
         count = a.shape[0] if a.ndim == 2 else a.size // (2 if kind == POLYGON else 4)

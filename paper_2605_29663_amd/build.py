@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libexact_mppi.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["capi.hip", "capi_batch.hip", "capi_mlp.hip", "kernels_sdf.hip", "kernels_step.hip",
-           "kernels_batch.hip", "kernels_mlp.hip"]
+           "kernels_batch.hip", "kernels_mlp.hip", "capi_cloud.hip", "kernels_cloud.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -37,6 +37,7 @@ int mppi_create(mppi_ctx* out, int device, void* hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard g(device);
     e = ctx->n_valid.ensure(sizeof(int));
+    if (e == hipSuccess) e = ctx->path.ensure(MPPI_MAX_PATH * sizeof(float2));
     if (e == hipSuccess) e = ctx->out.ensure(OUT_FLOATS * sizeof(float));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_out), OUT_FLOATS * sizeof(float), 0);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->n_valid.p, 0, sizeof(int), ctx->stream);
@@ -56,6 +57,8 @@ int mppi_destroy(mppi_ctx ctx) {
         (void)hipStreamSynchronize(ctx->stream);
         DevBuf* bufs[] = {&ctx->poly_verts, &ctx->poly_tab_a, &ctx->poly_tab_b, &ctx->rects,
                           &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
+                          &ctx->path, &ctx->cloud_keys, &ctx->cloud_first, &ctx->cloud_cell,
+                          &ctx->cloud_r2, &ctx->cloud_flag, &ctx->cloud_excl, &ctx->cloud_misc,
                           &ctx->eps_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
                           &ctx->key, &ctx->key64, &ctx->unew, &ctx->nom_poses,
                           &ctx->key_nom, &ctx->out};
@@ -171,6 +174,22 @@ int set_footprint(mppi_ctx ctx, int kind, const float* host, int count) {
     return fail(ctx, MPPI_E_ARG, "unknown footprint kind %d", kind);
 }
 
+int set_guidance(mppi_ctx ctx, const float* host_xy, int n) {
+    if (!ctx) return MPPI_E_ARG;
+    if (n < 0 || n > MPPI_MAX_PATH) return fail(ctx, MPPI_E_ARG, "guidance: n=%d outside [0, %d]", n, MPPI_MAX_PATH);
+    if (n > 0 && !host_xy) return fail(ctx, MPPI_E_ARG, "guidance: NULL waypoints");
+    for (int k = 0; k < 2 * n; ++k)
+        if (!std::isfinite(host_xy[k])) return fail(ctx, MPPI_E_ARG, "guidance: non-finite waypoint");
+    DeviceGuard g(ctx->device);
+    if (n > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->path.p, host_xy, sizeof(float2) * n, hipMemcpyHostToDevice,
+                                    ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    ctx->n_path = n;
+    return MPPI_OK;
+}
+
 int set_points(mppi_ctx ctx, const float* dx, const float* dy, const float* dvx, const float* dvy,
                const unsigned char* dvalid, int n) {
     if (!ctx) return MPPI_E_ARG;
@@ -278,7 +297,7 @@ int mppi_rollout(mppi_ctx ctx, const mppi_params* prm, const float* q0, const fl
         return fail(ctx, MPPI_E_CAPACITY, "K or T out of range");
     if (!valid_model(prm->model, prm->nu)) return fail(ctx, MPPI_E_ARG, "model/nu mismatch");
     DeviceGuard g(ctx->device);
-    const StepArgs A = make_args(prm, q0, seed, step);
+    const StepArgs A = make_args(ctx, prm, q0, seed, step);
     return rollout_into_ws(ctx, A, dU, dposes, deps, du, false);
 }
 
@@ -288,7 +307,7 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
     if (!q0 || !dU || !u_out) return fail(ctx, MPPI_E_ARG, "NULL argument");
     if (int rc = check_params(ctx, prm)) return rc;
     DeviceGuard g(ctx->device);
-    const StepArgs A = make_args(prm, q0, seed, step);
+    const StepArgs A = make_args(ctx, prm, q0, seed, step);
     const mppi_diag D = diag ? *diag : mppi_diag{};
     const int kind = prm->footprint_kind;
     const size_t Kpad = A.Kpad, T = A.T, nu = A.nu;
@@ -348,7 +367,7 @@ int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block
     if (reps < 1) reps = 3;
     DeviceGuard g(ctx->device);
     const float q0[3] = {0.f, 0.f, 0.f};
-    const StepArgs A = make_args(prm, q0, 0x7E57ull, 0);
+    const StepArgs A = make_args(ctx, prm, q0, 0x7E57ull, 0);
     // poses of one sampled step around a zero nominal
     HIP_TRY(ctx, ctx->unew.ensure(sizeof(float) * A.T * A.nu));
     HIP_TRY(ctx, hipMemsetAsync(ctx->unew.p, 0, sizeof(float) * A.T * A.nu, ctx->stream));

@@ -294,6 +294,7 @@ int fill_steps(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
         S.P.seed = seeds[s];
         S.P.step = steps[s];
         S.P.stream = b->noise_stream[s];
+        S.P.n_path = b->scenes[s]->n_path;  // guidance may change between steps
         S.U = dU + b->u_off[s];
     }
     return MPPI_OK;
@@ -373,7 +374,7 @@ int mppi_batch_create(mppi_batch* out, const mppi_ctx* scenes, const mppi_params
     b->noise_stream.assign(n, 0);
     const float zero3[3] = {0.f, 0.f, 0.f};
     for (int s = 0; s < n; ++s) {
-        b->args.push_back(make_args(&prms[s], zero3, 0, 0));
+        b->args.push_back(make_args(scenes[s], &prms[s], zero3, 0, 0));
         b->u_off[s + 1] = b->u_off[s] + prms[s].T * prms[s].nu;
     }
     DeviceGuard g(dev);

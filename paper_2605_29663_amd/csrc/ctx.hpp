@@ -71,6 +71,12 @@ struct mppi_ctx_s {
     int n_points = 0;
     bool moving = false;
     DevBuf px, py, pvx, pvy, pidx, n_valid;
+    // guidance polyline (fixed capacity MPPI_MAX_PATH waypoints, so the
+    // address a captured graph holds stays valid)
+    DevBuf path;
+    int n_path = 0;
+    // point-cloud pre-processing workspace
+    DevBuf cloud_keys, cloud_first, cloud_cell, cloud_r2, cloud_flag, cloud_excl, cloud_misc;
     // step workspaces
     DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom, out;
     float* h_out = nullptr;  // pinned
@@ -213,8 +219,12 @@ inline int check_params(mppi_ctx ctx, const mppi_params* p) {
     return MPPI_OK;
 }
 
-inline StepArgs make_args(const mppi_params* p, const float* q0, uint64_t seed, uint64_t step) {
+inline StepArgs make_args(mppi_ctx ctx, const mppi_params* p, const float* q0, uint64_t seed,
+                          uint64_t step) {
     StepArgs a{};
+    a.path = ctx->path.as<float2>();
+    a.n_path = ctx->n_path;
+    a.w_path = p->w_path;
     a.K = p->K;
     a.Kpad = (p->K + WAVE - 1) / WAVE * WAVE;
     a.T = p->T;

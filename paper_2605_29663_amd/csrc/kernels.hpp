@@ -20,6 +20,9 @@ struct StepArgs {
     float d_safe, w_coll, w_rep, w_inf, w_goal, w_ctrl[3], goal[2];
     float q0[3];
     uint64_t seed, step, stream;
+    const float2* path;  // guidance waypoints (planning frame)
+    int n_path;
+    float w_path;
 };
 
 // Valid obstacle points, compacted in index order (the count lives on the

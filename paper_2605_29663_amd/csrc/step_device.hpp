@@ -65,11 +65,34 @@ __device__ __forceinline__ void position_step(int model, const float u[3], float
     }
 }
 
+// Distance of (px, py) to the guidance polyline: min over its segments of
+// the clipped-projection point-segment distance (one waypoint: the distance
+// to it).
+__device__ __forceinline__ float path_dist(const float2* __restrict__ path, int n, float px,
+                                           float py) {
+    float2 a = path[0];
+    float best = (px - a.x) * (px - a.x) + (py - a.y) * (py - a.y);
+    for (int k = 1; k < n; ++k) {
+        const float2 b = path[k];
+        const float ex = b.x - a.x, ey = b.y - a.y;
+        const float wx = px - a.x, wy = py - a.y;
+        const float ee = ex * ex + ey * ey;
+        float t = ee > 0.0f ? (wx * ex + wy * ey) / ee : 0.0f;
+        t = fminf(fmaxf(t, 0.0f), 1.0f);
+        const float rx = wx - t * ex, ry = wy - t * ey;
+        best = fminf(best, rx * rx + ry * ry);
+        a = b;
+    }
+    return __builtin_sqrtf(best);
+}
+
 // Task + control terms of one scored state (the obstacle term is added once
-// the signed distances exist).
+// the signed distances exist): goal distance, guidance-path distance and the
+// control regulariser.
 __device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py, const float u[3]) {
     const float gx = px - P.goal[0], gy = py - P.goal[1];
     float v = P.w_goal * __builtin_sqrtf(gx * gx + gy * gy);
+    if (P.n_path > 0) v += P.w_path * path_dist(P.path, P.n_path, px, py);
     for (int c = 0; c < P.nu; ++c) v += P.w_ctrl[c] * (u[c] * u[c]);
     return v;
 }
@@ -80,8 +103,10 @@ __device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py
 //       sampled control (kept in LDS) and evaluates its heading rate;
 //   (b) wave 0, lane = rollout: the heading recursion (one fma per step);
 //   (c) every thread: sin / cos of its pair's new heading;
-//   (d) wave 0: the position recursion, the scored poses, the distance keys'
-//       initial values and the task + control costs.
+//   (d) wave 0: the position recursion, the scored poses and the distance
+//       keys' initial values;
+//   (e) every thread: the task + control terms of its pair, then wave 0 adds
+//       them up in step order.
 // lds: ROLL_LDS_FLOATS floats.
 __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __restrict__ U,
                                               const RolloutOut& o, int r0, float* lds) {
@@ -144,6 +169,7 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
                 s = cs.y;
                 if (P.state_offset) pose = make_float4(x, y, c, s);
                 o.poses[hk * Kpad + r] = pose;
+                scs[k * WAVE + lane] = make_float2(pose.x, pose.y);  // scored position
                 if (o.key) o.key[hk * Kpad + r] = DKEY_INIT;
                 if (o.key64) o.key64[hk * Kpad + r] = DKEY64_INIT;
                 if (o.diag_poses && r < P.K) {
@@ -153,9 +179,18 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
                     dp[2] = pose.z;
                     dp[3] = pose.w;
                 }
-                jb += task_ctrl(P, pose.x, pose.y, u);
             }
         }
+        __syncthreads();
+        if (hh < hn) {
+            const float2 p = scs[hh * WAVE + lane];
+            const float u[3] = {su[(hh * 3) * WAVE + lane], su[(hh * 3 + 1) * WAVE + lane],
+                                su[(hh * 3 + 2) * WAVE + lane]};
+            sw[hh * WAVE + lane] = task_ctrl(P, p.x, p.y, u);
+        }
+        __syncthreads();
+        if (chain)
+            for (int k = 0; k < hn; ++k) jb += sw[k * WAVE + lane];
         __syncthreads();
     }
     if (chain) o.jbase[r] = jb;

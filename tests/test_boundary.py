@@ -68,9 +68,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_struct_layout_matches_header():
     """The ctypes mirror of mppi_params has the C layout: 5 ints, 3 floats,
-    3x3 float arrays, 5 floats, 3 floats, 2 floats, 2 ints."""
+    3x3 float arrays, 5 floats, 3 floats, 2 floats, 2 ints, 1 float."""
     import paper_2605_29663_amd as pkg
-    assert ctypes.sizeof(pkg.MppiParams) == 4 * (5 + 3 + 9 + 5 + 3 + 2 + 2)
+    assert ctypes.sizeof(pkg.MppiParams) == 4 * (5 + 3 + 9 + 5 + 3 + 2 + 2 + 1)
+    assert pkg.MppiParams.w_path.offset == 4 * (5 + 3 + 9 + 5 + 3 + 2 + 2)
     assert pkg.MppiParams.goal.offset == 4 * (5 + 3 + 9 + 5 + 3)
     assert ctypes.sizeof(pkg.MppiDiag) == 10 * 8
     # mppi_hybrid_params: float, int32, 4 floats

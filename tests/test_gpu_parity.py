@@ -286,6 +286,38 @@ def test_step_parity_small(ctx, pkg, orc, name, K, N, T):
     _check_step_rows(orc, prm, sc, q0, U0, 0x5EED, 3, u_star, valid, D, Ut)
 
 
+@pytest.mark.parametrize("name,path", [("c2", [(0.0, 0.0), (2.0, 0.3), (2.0, 0.3), (4.0, -1.0)]),
+                                       ("c1", [(1.0, 0.5)])])
+def test_step_parity_with_guidance(ctx, pkg, orc, name, path):
+    """Path-following task term: the GPU's J~ and J_nom against the oracle's
+    costs with the same polyline (repeated waypoint and single waypoint)."""
+    import torch
+    prm, sc = _step_case(name, 128 if name == "c2" else None, 1200 if name == "c2" else None)
+    prm = dict(prm, w_path=1.5, path=path)
+    _load_scene(ctx, pkg, prm, sc)
+    ctx.set_guidance(path)
+    try:
+        U0 = np.zeros((prm["T"], prm["nu"]), np.float32)
+        q0 = np.float32([0.1, 0.05, -0.02])
+        Ut = torch.tensor(U0, device="cuda")
+        u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=5, step=1, diag=True)
+        Jt = _check_step_rows(orc, prm, sc, q0, U0, 5, 1, u_star, valid, D, Ut)
+        # the term is really there: without the path the costs differ
+        J_plain = orc.costs(dict(prm, path=None), _np(D["poses"])[..., :2], _np(D["u"]),
+                            _np(D["d_min"]).astype(np.float64))[2]
+        assert np.all(Jt > J_plain)
+    finally:
+        ctx.set_guidance(None)
+
+
+def test_guidance_errors(ctx, pkg):
+    with pytest.raises(pkg.MppiError):
+        ctx.set_guidance(np.zeros((65, 2), np.float32))
+    with pytest.raises(pkg.MppiError):
+        ctx.set_guidance([(0.0, 0.0), (np.nan, 1.0)])
+    ctx.set_guidance(None)
+
+
 def test_step_matches_oracle_from_scratch_c1(ctx, pkg, orc):
     """End to end on the small unicycle case: the oracle runs the whole cycle
     itself (double-precision SDF, costs, update, validation)."""

@@ -97,3 +97,24 @@ def test_step_moves_towards_goal(orc):
         out = orc.mppi_step(prm, np.zeros(3, np.float32), U, scene, 5, step)
         U = out["U_next"].astype(np.float32)
     assert U[:5, 0].mean() > 0.3
+
+
+def test_path_following_term_hand_values(orc):
+    """w_path x distance to the guidance polyline (0,0)-(2,0)-(2,2): inside a
+    segment's slab it is the perpendicular distance, beyond the ends the
+    distance to the end vertex; a repeated waypoint is a point; one waypoint
+    gives the distance to it.  w_goal = 0 isolates the term."""
+    from paper_2605_29663_amd import scenes
+    prm = scenes.params("c1", w_goal=0.0, w_path=2.0, path=[(0, 0), (2, 0), (2, 2)])
+    for (x, y), d in (((1.0, 0.5), 0.5), ((3.0, 1.0), 1.0), ((-1.0, 0.0), 1.0),
+                      ((3.0, 3.0), math.sqrt(2.0)), ((2.0, 1.0), 0.0), ((1.5, -0.25), 0.25)):
+        assert abs(orc.phi_task(prm, x, y) - 2.0 * d) < 1e-12, (x, y)
+    rep = scenes.params("c1", w_goal=0.0, w_path=1.0, path=[(0, 0), (0, 0), (1, 0)])
+    assert abs(orc.phi_task(rep, 0.5, 1.0) - 1.0) < 1e-12
+    assert abs(orc.phi_task(rep, -3.0, 4.0) - 5.0) < 1e-12
+    one = scenes.params("c1", w_goal=0.0, w_path=1.0, path=[(1.0, 1.0)])
+    assert abs(orc.phi_task(one, 4.0, 5.0) - 5.0) < 1e-12
+    # no path: only the goal term
+    g = scenes.params("c1", goal=(3.0, 4.0))
+    assert abs(orc.phi_task(g, 0.0, 0.0) - 5.0) < 1e-6
+    assert abs(orc.phi_task(dict(g, w_path=7.0), 0.0, 0.0) - 5.0) < 1e-6
