@@ -25,7 +25,7 @@ POLYGON, RECTS = 0, 1
 MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
-           "set_footprint", "set_points", "set_guidance",
+           "set_footprint", "set_points", "set_guidance", "cloud_downsample",
            "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
            "mppi_autotune", "mppi_tune_get", "mppi_tune_set", "mppi_set_tiles",
            "mppi_set_profiling", "mppi_get_profile",
@@ -57,6 +57,11 @@ class MppiParams(ctypes.Structure):
                 ("w_goal", ctypes.c_float), ("w_ctrl", ctypes.c_float * 3),
                 ("goal", ctypes.c_float * 2), ("state_offset", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("w_path", ctypes.c_float)]
+
+
+class CloudParams(ctypes.Structure):
+    _fields_ = [("z_min", ctypes.c_float), ("z_max", ctypes.c_float), ("r_max", ctypes.c_float),
+                ("voxel", ctypes.c_float), ("n_out", ctypes.c_int32)]
 
 
 class HybridParams(ctypes.Structure):
@@ -98,6 +103,8 @@ def load():
     L.set_footprint.argtypes = [vp, i, vp, i]
     L.set_points.argtypes = [vp, vp, vp, vp, vp, vp, i]
     L.set_guidance.argtypes = [vp, vp, i]
+    L.cloud_downsample.argtypes = [vp, vp, i, vp, ctypes.POINTER(CloudParams), vp, vp, vp,
+                                   ctypes.POINTER(i)]
     L.sdf_polygon.argtypes = [vp, vp, vp, i, vp]
     L.sdf_rectcover.argtypes = [vp, vp, vp, i, vp]
     L.sdf_min_poses.argtypes = [vp, vp, i, i, f, i, i, vp, vp]
@@ -239,6 +246,21 @@ class Context:
             return
         a = np.ascontiguousarray(np.asarray(waypoints, dtype=np.float32).reshape(-1, 2))
         self._check(self.lib.set_guidance(self.h, a.ctypes.data_as(ctypes.c_void_p), a.shape[0]))
+
+    def cloud_downsample(self, xyz, center, z_min, z_max, r_max, voxel, n_out):
+        """Height band + range filter and voxel downsampling of a device (m, 3)
+        cloud to n_out slots.  Returns (x, y, valid, n_kept), device outputs."""
+        xyz = _dev_f32(xyz, self.device, "xyz").reshape(-1, 3)
+        m = xyz.shape[0]
+        x = torch.empty(max(n_out, 1), dtype=torch.float32, device=self.device)
+        y = torch.empty_like(x)
+        valid = torch.empty(max(n_out, 1), dtype=torch.uint8, device=self.device)
+        cp = CloudParams(float(z_min), float(z_max), float(r_max), float(voxel), int(n_out))
+        c = (ctypes.c_float * 2)(float(center[0]), float(center[1]))
+        k = ctypes.c_int(0)
+        self._check(self.lib.cloud_downsample(self.h, _ptr(xyz), m, c, ctypes.byref(cp), _ptr(x),
+                                              _ptr(y), _ptr(valid), ctypes.byref(k)))
+        return x[:n_out], y[:n_out], valid[:n_out], k.value
 
     def set_footprint(self, kind, data):
         a = np.ascontiguousarray(np.asarray(data, dtype=np.float32))

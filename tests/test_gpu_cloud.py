@@ -1,0 +1,112 @@
+"""Point-cloud pre-processing on the GPU against the oracle: bit-identical
+outputs (positions, mask, kept count) on random clouds spanning one to many
+scan blocks, the budget above and below the number of occupied voxels,
+repeated points, range ties, non-finite points, the maximum size, the empty
+and degenerate cases; determinism; argument errors; and the hand-over to
+set_points and one MPPI step."""
+import numpy as np
+import pytest
+
+from paper_2605_29663_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_29663_amd as pkg
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def _cloud(rng, m, spread=8.0, dup=0.2, nan=0.005):
+    p = rng.uniform(-spread, spread, (m, 3)).astype(np.float32)
+    p[:, 2] = rng.uniform(-1.0, 2.0, m).astype(np.float32)
+    if m > 1:
+        d = rng.integers(0, m, int(m * dup))
+        p[d] = p[rng.integers(0, m, d.size)]
+    p[rng.random(m) < nan, int(rng.integers(0, 3))] = np.nan
+    return p
+
+
+def _check(ctx, p, center, z_min, z_max, r_max, voxel, n_out):
+    import torch
+    from oracle import cloud
+    x, y, v, k = ctx.cloud_downsample(torch.tensor(p, device="cuda"), center, z_min, z_max,
+                                      r_max, voxel, n_out)
+    xo, yo, vo, ko = cloud.downsample(p, center, z_min, z_max, r_max, voxel, n_out)
+    assert k == ko
+    np.testing.assert_array_equal(x.cpu().numpy(), xo)
+    np.testing.assert_array_equal(y.cpu().numpy(), yo)
+    np.testing.assert_array_equal(v.cpu().numpy(), vo)
+    return k
+
+
+@pytest.mark.parametrize("m,n_out,voxel", [(1, 4, 0.1), (700, 50, 0.2), (700, 5000, 0.2),
+                                           (5000, 1024, 0.05), (200000, 8192, 0.05),
+                                           (200000, 100, 0.5), (1 << 20, 8192, 0.02)])
+def test_cloud_matches_oracle(ctx, m, n_out, voxel):
+    rng = np.random.default_rng(m + n_out)
+    p = _cloud(rng, m)
+    k = _check(ctx, p, (0.3, -0.2), 0.0, 1.5, 6.0, voxel, n_out)
+    assert k <= n_out
+
+
+def test_cloud_ties_and_degenerate_cases(ctx):
+    # a ring of equal ranges (ties broken by index) in distinct voxels
+    ang = np.arange(64) * (2 * np.pi / 64)
+    ring = np.stack([2 * np.cos(ang), 2 * np.sin(ang), np.zeros(64)], 1).astype(np.float32)
+    ring = np.concatenate([ring, ring[::-1]])            # every point twice
+    for n_out in (0, 1, 10, 64, 100):
+        _check(ctx, ring, (0.0, 0.0), -1, 1, 3.0, 0.01, n_out)
+    # everything in one voxel, everything filtered, empty input
+    one = np.tile(np.float32([[0.11, 0.12, 0.0]]), (3000, 1))
+    assert _check(ctx, one, (0, 0), -1, 1, 1.0, 1.0, 16) == 1
+    assert _check(ctx, one, (0, 0), 0.5, 1, 1.0, 1.0, 16) == 0
+    assert _check(ctx, np.zeros((0, 3), np.float32), (0, 0), -1, 1, 1.0, 1.0, 16) == 0
+    # points at the robot (zero range), exactly on r_max and voxel borders
+    pts = np.float32([[0, 0, 0], [3, 4, 0], [1.0, 1.0, 0], [-1.0, -1.0, 0], [2.5, 0, 0]])
+    _check(ctx, pts, (0.0, 0.0), -1, 1, 5.0, 0.5, 3)
+
+
+def test_cloud_deterministic_and_errors(ctx):
+    import torch
+    import paper_2605_29663_amd as pkg
+    rng = np.random.default_rng(7)
+    p = torch.tensor(_cloud(rng, 100000), device="cuda")
+    a = ctx.cloud_downsample(p, (0, 0), 0, 1.5, 6, 0.05, 4096)
+    b = ctx.cloud_downsample(p, (0, 0), 0, 1.5, 6, 0.05, 4096)
+    assert all(torch.equal(u, w) for u, w in zip(a[:3], b[:3])) and a[3] == b[3]
+    for bad in (dict(voxel=0.0), dict(r_max=-1.0), dict(z_min=2.0), dict(voxel=1e-9),
+                dict(n_out=-1)):
+        kw = dict(center=(0, 0), z_min=0.0, z_max=1.5, r_max=6.0, voxel=0.05, n_out=16)
+        kw.update(bad)
+        with pytest.raises(pkg.MppiError):
+            ctx.cloud_downsample(p, **kw)
+    with pytest.raises(pkg.MppiError):
+        ctx.cloud_downsample(torch.zeros(((1 << 20) + 1, 3), device="cuda"), (0, 0), 0, 1, 1, 1, 4)
+
+
+def test_cloud_feeds_the_step(ctx, orc):
+    """Downsampled points go to set_points on the device; the step's signed
+    distances then match the oracle on the kept points."""
+    import torch
+    import paper_2605_29663_amd as pkg
+    rng = np.random.default_rng(3)
+    p = _cloud(rng, 50000, spread=4.0, nan=0.0)
+    x, y, v, k = ctx.cloud_downsample(torch.tensor(p, device="cuda"), (0, 0), -0.5, 1.5, 4.0,
+                                      0.1, 512)
+    prm = scenes.params("c1", K=64, T=10)
+    ctx.set_footprint(pkg.POLYGON, scenes.FOOTPRINT_L8)
+    ctx.set_points(x, y, valid=v)
+    U = torch.zeros((10, 2), device="cuda")
+    _, _, D = ctx.mppi_step(prm, np.zeros(3, np.float32), U, 1, 0, diag=True)
+    keep = v.cpu().numpy().astype(bool)
+    poses = D["poses"].cpu().numpy().reshape(-1, 4)
+    d_o = orc.dmin(poses, orc.tau_of(prm, 10, 64).ravel(), x.cpu().numpy()[keep],
+                   y.cpu().numpy()[keep], None, None, None, 0, scenes.FOOTPRINT_L8)
+    np.testing.assert_allclose(D["d_min"].cpu().numpy().ravel(), d_o, atol=1e-5)
