@@ -39,7 +39,7 @@ __global__ __launch_bounds__(ROLL_THREADS) void k_rollout_b(const SceneStep* __r
 }
 
 // Footprint bucket dispatch.  Class 0: polygons up to 16 padded vertices
-// (register budget for 3 waves per SIMD); class 1: polygons of 20..32
+// (register budget for 3 waves per SIMD); class 1: polygons of 18..32
 // padded vertices (2 waves); class 2: rectangle covers (2 waves: up to 32
 // boxes are kept in registers).
 template <int CLS>
@@ -63,8 +63,11 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
     if (CLS == 0) {
         switch (S.padded) {
             EMPPI_POLY(4)
+            EMPPI_POLY(6)
             EMPPI_POLY(8)
+            EMPPI_POLY(10)
             EMPPI_POLY(12)
+            EMPPI_POLY(14)
             EMPPI_POLY(16)
         default: break;
         }
@@ -86,9 +89,13 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
         }
     } else {
         switch (S.padded) {
+            EMPPI_POLY(18)
             EMPPI_POLY(20)
+            EMPPI_POLY(22)
             EMPPI_POLY(24)
+            EMPPI_POLY(26)
             EMPPI_POLY(28)
+            EMPPI_POLY(30)
             EMPPI_POLY(32)
         default: break;
         }

@@ -222,7 +222,9 @@ hipError_t launch_rect(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s
 }  // namespace
 
 int dmin_padded_count(int kind, int count) {
-    if (kind == 0) return ((count + 3) / 4) * 4 < 4 ? 4 : ((count + 3) / 4) * 4;
+    // polygons: even vertex counts (padding repeats vertex 0: zero-length
+    // edges that change neither the minimum nor the crossing parity)
+    if (kind == 0) return count <= 4 ? 4 : ((count + 1) / 2) * 2;
     static const int rb[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int b : rb)
         if (count <= b) return b;
@@ -234,14 +236,12 @@ hipError_t launch_dmin(const DminLaunch& L, hipStream_t s) {
     const size_t lds = static_cast<size_t>(DMIN_TILE) * (L.pts.vx ? 16 : 8);
     if (L.kind == 0) {
         switch (L.padded) {
-        case 4: return launch_poly<4>(L, grid, lds, s);
-        case 8: return launch_poly<8>(L, grid, lds, s);
-        case 12: return launch_poly<12>(L, grid, lds, s);
-        case 16: return launch_poly<16>(L, grid, lds, s);
-        case 20: return launch_poly<20>(L, grid, lds, s);
-        case 24: return launch_poly<24>(L, grid, lds, s);
-        case 28: return launch_poly<28>(L, grid, lds, s);
-        case 32: return launch_poly<32>(L, grid, lds, s);
+#define EMPPI_CASE(P) \
+    case P: return launch_poly<P>(L, grid, lds, s);
+            EMPPI_CASE(4) EMPPI_CASE(6) EMPPI_CASE(8) EMPPI_CASE(10) EMPPI_CASE(12) EMPPI_CASE(14)
+            EMPPI_CASE(16) EMPPI_CASE(18) EMPPI_CASE(20) EMPPI_CASE(22) EMPPI_CASE(24)
+            EMPPI_CASE(26) EMPPI_CASE(28) EMPPI_CASE(30) EMPPI_CASE(32)
+#undef EMPPI_CASE
         default: return hipErrorInvalidValue;
         }
     }
