@@ -50,6 +50,9 @@ def parse():
                     help="re-tune the tile shapes instead of using the shipped table")
     ap.add_argument("--cpu-reps", type=int, default=4,
                     help="whole oracle steps timed for the CPU baseline")
+    ap.add_argument("--graph", action="store_true",
+                    help="time steps replayed from a captured graph (the distance kernel is then "
+                         "timed on as many eager steps right after)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), "
                          "the reference kernel for scaling the HBM byte counters")
@@ -218,10 +221,13 @@ def main():
     else:
         tuned = ctx.mppi_autotune(None, reps=3, params=params)
         tile_source = "autotuned in this run"
+    if args.graph:
+        ctx.mppi_set_graph(True)
     for i in range(args.warmup):
         ctx.mppi_step(None, q0, U, seed, i, params=params)
     torch.cuda.synchronize()
-    ctx.mppi_set_profiling(True)
+    if not args.graph:
+        ctx.mppi_set_profiling(True)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -231,6 +237,13 @@ def main():
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if args.graph:
+        # the distance kernel timed on as many eager steps
+        ctx.mppi_set_graph(False)
+        ctx.mppi_set_profiling(True)
+        for i in range(args.steps):
+            ctx.mppi_step(None, q0, U, seed, args.warmup + args.steps + i, params=params)
+        torch.cuda.synchronize()
     k_ms, k_n = ctx.mppi_get_profile()
     ctx.mppi_set_profiling(False)
 
@@ -259,6 +272,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded scene generator)",
+        "execution": "hipGraph replay" if args.graph else "eager launches",
         "config": {"workload": {"c1": "unicycle open field", "c2": "ackermann corridor",
                                 "c3": "omni rectangle cover, moving points"}[args.config],
                    "K": K, "T": T, "N": N, ("B" if kind == 0 else "R"): P,

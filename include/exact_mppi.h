@@ -93,6 +93,14 @@ typedef struct mppi_params {
     float w_path;
 } mppi_params;
 
+/* Graph mode (enable != 0): mppi_step calls without diagnostics (diag NULL)
+ * and without profiling replay a captured hipGraph of the whole step (a
+ * one-scene batch of this context, see mppi_batch_create: bit-identical
+ * results, fewer launch overheads).  The graph is rebuilt when the
+ * parameters change and re-planned when points or footprint change.  The
+ * call first waits for the context's stream.  Disabling frees it.          */
+MPPI_API int mppi_set_graph(mppi_ctx ctx, int enable);
+
 /* Weak guidance (Section "Problem Statement": a waypoint sequence from an
  * upstream module; the task term's "path following"): host array of n
  * planning-frame waypoints (x0, y0, x1, y1, ...), copied synchronously into

@@ -27,7 +27,7 @@ MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
            "set_footprint", "set_points", "set_guidance", "cloud_downsample",
            "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
-           "mppi_autotune", "mppi_tune_get", "mppi_tune_set", "mppi_set_tiles",
+           "mppi_autotune", "mppi_tune_get", "mppi_tune_set", "mppi_set_tiles", "mppi_set_graph",
            "mppi_set_profiling", "mppi_get_profile",
            "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
            "mppi_batch_u_offsets", "mppi_batch_refresh", "mppi_step_batched",
@@ -114,6 +114,7 @@ def load():
     L.mppi_autotune.argtypes = [vp, ctypes.POINTER(MppiParams), i, ctypes.POINTER(i),
                                 ctypes.POINTER(i)]
     L.mppi_set_tiles.argtypes = [vp, i, i]
+    L.mppi_set_graph.argtypes = [vp, i]
     L.mppi_tune_get.argtypes = [vp, ctypes.c_char_p, i]
     L.mppi_tune_set.argtypes = [vp, ctypes.c_char_p]
     L.mppi_set_profiling.argtypes = [vp, i]
@@ -335,6 +336,10 @@ class Context:
 
     def mppi_tune_set(self, text):
         self._check(self.lib.mppi_tune_set(self.h, text.encode()))
+
+    def mppi_set_graph(self, enable=True):
+        """Replay steps without diagnostics from a captured graph (bit-identical)."""
+        self._check(self.lib.mppi_set_graph(self.h, int(bool(enable))))
 
     def mppi_set_tiles(self, block=0, nchunk=0):
         self._check(self.lib.mppi_set_tiles(self.h, int(block), int(nchunk)))

@@ -55,6 +55,7 @@ int mppi_destroy(mppi_ctx ctx) {
     {
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
+        if (ctx->gbatch) mppi_batch_destroy(ctx->gbatch);
         DevBuf* bufs[] = {&ctx->poly_verts, &ctx->poly_tab_a, &ctx->poly_tab_b, &ctx->rects,
                           &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
                           &ctx->path, &ctx->cloud_keys, &ctx->cloud_first, &ctx->cloud_cell,
@@ -301,12 +302,58 @@ int mppi_rollout(mppi_ctx ctx, const mppi_params* prm, const float* q0, const fl
     return rollout_into_ws(ctx, A, dU, dposes, deps, du, false);
 }
 
+int mppi_set_graph(mppi_ctx ctx, int enable) {
+    if (!ctx) return MPPI_E_ARG;
+    ctx->graph_mode = enable != 0;
+    if (!ctx->graph_mode && ctx->gbatch) {
+        DeviceGuard g(ctx->device);
+        mppi_batch_destroy(ctx->gbatch);
+        ctx->gbatch = nullptr;
+    }
+    return MPPI_OK;
+}
+
+namespace {
+
+// Graph-mode step: a one-scene batch of this context (bit-identical to the
+// eager step), rebuilt when the parameters change and re-planned when the
+// points or the footprint changed.
+int step_via_graph(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, uint64_t seed,
+                   uint64_t step, float* u_out, int* valid_out) {
+    if (ctx->gbatch && std::memcmp(&ctx->gprm, prm, sizeof(mppi_params)) != 0) {
+        mppi_batch_destroy(ctx->gbatch);
+        ctx->gbatch = nullptr;
+    }
+    if (!ctx->gbatch) {
+        if (int rc = mppi_batch_create(&ctx->gbatch, &ctx, prm, 1, nullptr))
+            return fail(ctx, rc, "graph mode: %s", mppi_batch_last_error(nullptr));
+        ctx->gprm = *prm;
+    }
+    // work the caller queued on the context's stream (nominal, points) comes first
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    int valid = 0;
+    float u3[3];
+    int rc = mppi_step_batched(ctx->gbatch, q0, dU, &seed, &step, u3, &valid, 1);
+    if (rc == MPPI_E_STATE) {
+        if ((rc = mppi_batch_refresh(ctx->gbatch)) == MPPI_OK)
+            rc = mppi_step_batched(ctx->gbatch, q0, dU, &seed, &step, u3, &valid, 1);
+    }
+    if (rc) return fail(ctx, rc, "graph mode: %s", mppi_batch_last_error(ctx->gbatch));
+    for (int c = 0; c < prm->nu; ++c) u_out[c] = u3[c];
+    if (valid_out) *valid_out = valid;
+    return MPPI_OK;
+}
+
+}  // namespace
+
 int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, uint64_t seed,
               uint64_t step, float* u_out, int* valid_out, const mppi_diag* diag) {
     if (!ctx) return MPPI_E_ARG;
     if (!q0 || !dU || !u_out) return fail(ctx, MPPI_E_ARG, "NULL argument");
     if (int rc = check_params(ctx, prm)) return rc;
     DeviceGuard g(ctx->device);
+    if (ctx->graph_mode && !diag && !ctx->prof)
+        return step_via_graph(ctx, prm, q0, dU, seed, step, u_out, valid_out);
     const StepArgs A = make_args(ctx, prm, q0, seed, step);
     const mppi_diag D = diag ? *diag : mppi_diag{};
     const int kind = prm->footprint_kind;

@@ -83,6 +83,10 @@ struct mppi_ctx_s {
     // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
     std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
     int force_block = 0, force_nchunk = 0;  // mppi_set_tiles
+    // graph mode: steps without diagnostics replay a captured one-scene batch
+    bool graph_mode = false;
+    mppi_batch gbatch = nullptr;
+    mppi_params gprm{};
     // profiling of the dominant launch
     bool prof = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
