@@ -140,8 +140,9 @@ int plan(mppi_batch b, double work_per_item) {
         const int padded = kind == 0 ? c->BP : c->RP;
         const size_t Kpad = b->args[s].Kpad, T = P.T, nu = P.nu;
         const int npts = std::max(c->n_points, 0);
-        // rollout pass: pose tiles of 256 lanes, chunks sized for the target work
-        const double per_point = 256.0 * padded;
+        // rollout pass: pose tiles of 256 lanes (128 poses where a lane pair
+        // shares a pose), chunks sized for the target work
+        const double per_point = 256.0 / dmin_persistent_lanes_per_pose(dmin_class(kind, padded)) * padded;
         int ck = static_cast<int>(std::max(32.0, std::min(static_cast<double>(std::max(npts, 1)),
                                                           work_per_item / per_point)));
         nchunk[s] = std::max(1, (npts + ck - 1) / ck);
@@ -194,7 +195,7 @@ int plan(mppi_batch b, double work_per_item) {
             D.rects = c->rects.as<float4>();
             D.key = pass == 0 ? B.key : B.key_nom;
             if (pass == 1 && !P.validate) continue;
-            const int tile = pass == 0 ? 256 : 128;
+            const int tile = (pass == 0 ? 256 : 128) / dmin_persistent_lanes_per_pose(cls);
             const int nck = pass == 0 ? nchunk[s] : nchunk_nom[s];
             for (int g0 = 0; g0 < D.npose; g0 += tile) {
                 const int live = std::min(tile, D.npose - g0);

@@ -177,6 +177,7 @@ hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs,
 hipError_t launch_finalize_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
                                    hipStream_t s);
 int dmin_persistent_waves(int cls);
+int dmin_persistent_lanes_per_pose(int cls);
 
 // ---------------------------------------------------------------- hybrid modes
 constexpr int HYB_MAX_MODES = 8;

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(ROLL_THREADS) void k_rollout_b(const SceneStep* __r
 
 // Footprint bucket dispatch.  Class 0: polygons up to 16 padded vertices
 // (register budget for 3 waves per SIMD); class 1: polygons of 18..32
-// padded vertices (2 waves); class 2: rectangle covers (2 waves: up to 32
+// padded vertices, a lane pair per pose, each lane holding half the edges
+// (3 waves); class 2: rectangle covers (2 waves: up to 32
 // boxes are kept in registers).
 template <int CLS>
 __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, float4 q, float tau,
@@ -52,6 +53,13 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
             dmin_poly_range<P, true, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);   \
         else                                                                                  \
             dmin_poly_range<P, false, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);  \
+        return;
+#define EMPPI_PAIR(P)                                                                         \
+    case P:                                                                                   \
+        if (moving)                                                                           \
+            dmin_poly_pair_range<P / 2, true>(q, tau, S.pts, c0, c1, S.verts, lds, best);     \
+        else                                                                                  \
+            dmin_poly_pair_range<P / 2, false>(q, tau, S.pts, c0, c1, S.verts, lds, best);    \
         return;
 #define EMPPI_RECT(P)                                                                         \
     case P:                                                                                   \
@@ -89,25 +97,26 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
         }
     } else {
         switch (S.padded) {
-            EMPPI_POLY(18)
-            EMPPI_POLY(20)
-            EMPPI_POLY(22)
-            EMPPI_POLY(24)
-            EMPPI_POLY(26)
-            EMPPI_POLY(28)
-            EMPPI_POLY(30)
-            EMPPI_POLY(32)
+            EMPPI_PAIR(18)
+            EMPPI_PAIR(20)
+            EMPPI_PAIR(22)
+            EMPPI_PAIR(24)
+            EMPPI_PAIR(26)
+            EMPPI_PAIR(28)
+            EMPPI_PAIR(30)
+            EMPPI_PAIR(32)
         default: break;
         }
     }
 #undef EMPPI_POLY
+#undef EMPPI_PAIR
 #undef EMPPI_RECT
     best = INFINITY;  // unreachable for planned items
 }
 
 template <int CLS>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(CLS == 0 ? 3 : 2)))
+__attribute__((amdgpu_waves_per_eu(CLS == 2 ? 2 : 3)))
 void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __restrict__ items,
                        int n_items, int* __restrict__ counter) {
     extern __shared__ float lds[];
@@ -120,7 +129,8 @@ void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __rest
         if (it >= n_items) break;
         const DminItem w = items[it];
         const SceneDmin& S = sds[w.sd];
-        const int g = w.g0 + static_cast<int>(threadIdx.x);
+        // class 1: two lanes per pose
+        const int g = w.g0 + static_cast<int>(CLS == 1 ? threadIdx.x >> 1 : threadIdx.x);
         const int npose = S.npose;
         const bool live = g < npose;
         const float4 q = live ? S.poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
@@ -131,7 +141,7 @@ void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __rest
         const int c1 = min(c0 + S.chunk, nv);
         float best;
         dmin_dispatch<CLS>(S, moving, q, tau, c0, c1, lds, best);
-        if (live) atomicMin(&S.key[g], dkey(best));
+        if (live && (CLS != 1 || (threadIdx.x & 1) == 0)) atomicMin(&S.key[g], dkey(best));
     }
 }
 
@@ -232,7 +242,8 @@ hipError_t launch_hybrid_select(const float* out, const HybridArgs& a, float* re
     return hipGetLastError();
 }
 
-int dmin_persistent_waves(int cls) { return cls == 0 ? 3 : 2; }
+int dmin_persistent_waves(int cls) { return cls == 2 ? 2 : 3; }
+int dmin_persistent_lanes_per_pose(int cls) { return cls == 1 ? 2 : 1; }
 
 hipError_t launch_batch_reset(int* counters, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counters, n);

@@ -155,6 +155,76 @@ struct PolyFrame {
     }
 };
 
+// Half of a footprint of 2 HB (padded) vertices for a pair of lanes that
+// share one pose: the lane of parity h holds edges [h HB, (h + 1) HB), rotated
+// exactly as in PolyFrame, and the y of the vertex closing its last edge.
+// Halving the per-lane registers lets large polygons run at the occupancy of
+// small ones; the pair's partial minima and crossing parities are combined
+// per point (min and parity are exact, so the result is the same bits as
+// one lane holding every edge).
+template <int HB>
+struct PolyHalf {
+    float X[HB], Y[HB], EX[HB], EY[HB], SX[HB], SY[HB], SL[HB];
+    float Yend;
+
+    __device__ __forceinline__ void init(const float2* __restrict__ verts, int b0, float c, float s) {
+#pragma unroll
+        for (int b = 0; b < HB; ++b) {
+            const float2 v = verts[b0 + b];
+            X[b] = __builtin_fmaf(c, v.x, -(s * v.y));
+            Y[b] = __builtin_fmaf(s, v.x, c * v.y);
+        }
+        const float2 vn = verts[(b0 + HB) % (2 * HB)];
+        const float Xn = __builtin_fmaf(c, vn.x, -(s * vn.y));
+        const float Yn = __builtin_fmaf(s, vn.x, c * vn.y);
+#pragma unroll
+        for (int b = 0; b < HB; ++b) {
+            const float nx = b + 1 < HB ? X[b + 1] : Xn;
+            const float ny = b + 1 < HB ? Y[b + 1] : Yn;
+            EX[b] = nx - X[b];
+            EY[b] = ny - Y[b];
+            const float l2 = __builtin_fmaf(EX[b], EX[b], EY[b] * EY[b]);
+            const float inv = l2 > 0.0f ? 1.0f / l2 : 0.0f;
+            SX[b] = EX[b] * inv;
+            SY[b] = EY[b] * inv;
+            SL[b] = EY[b] != 0.0f ? EX[b] / EY[b] : 0.0f;
+        }
+        Yend = Yn;
+    }
+
+    // Minimum squared distance over this lane's edges and the parity of
+    // their crossings of the ray from (dx, dy).
+    __device__ __forceinline__ void eval(float dx, float dy, float& m, bool& odd) const {
+        EdgeEval e = edge_eval(dx, dy, X[0], Y[0], EX[0], EY[0], SX[0], SY[0], SL[0]);
+        m = e.d2;
+        bool above = e.above, right = e.right;
+        odd = false;
+#pragma unroll
+        for (int b = 1; b < HB; ++b) {
+            e = edge_eval(dx, dy, X[b], Y[b], EX[b], EY[b], SX[b], SY[b], SL[b]);
+            m = fminf(m, e.d2);
+            odd ^= (above != e.above) & right;
+            above = e.above;
+            right = e.right;
+        }
+        odd ^= (above != ((dy - Yend) < 0.0f)) & right;
+    }
+};
+
+// Value of the other lane of the pair (lanes 2k, 2k + 1): DPP quad
+// permutation [1, 0, 3, 2].
+__device__ __forceinline__ float pair_swap(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Signed squared distance from a lane pair's partial results: the smaller
+// minimum, negative when exactly one half saw an odd number of crossings.
+__device__ __forceinline__ float pair_combine(float m, bool odd) {
+    const float sg = odd ? -1.0f : 1.0f;
+    const float mm = fminf(m, pair_swap(m));
+    return (sg * pair_swap(sg)) * mm;
+}
+
 // Min over the valid points [c0, c1) of the signed squared distance to the
 // polygon for the pose (q, tau) held by this lane.  All threads of the
 // workgroup must call it (LDS staging uses barriers).
@@ -187,6 +257,41 @@ __device__ __forceinline__ void dmin_poly_range(float4 q, float tau, const Point
             float dx, dy;
             point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
             take<ARGMIN>(F.eval(dx, dy), t0 + i, best, besti);
+        }
+    }
+}
+
+// Same with a lane pair per pose (2 HB padded vertices, see PolyHalf); both
+// lanes of a pair return the pose's minimum.  Every lane of the workgroup
+// must call it with the same range.
+template <int HB, bool MOVING>
+__device__ __forceinline__ void dmin_poly_pair_range(float4 q, float tau, const PointArgs& pts,
+                                                     int c0, int c1, const float2* __restrict__ verts,
+                                                     float* lds, float& best) {
+    PolyHalf<HB> F;
+    F.init(verts, (threadIdx.x & 1) * HB, q.z, q.w);
+    best = INFINITY;
+    for (int t0 = c0; t0 < c1; t0 += DMIN_TILE) {
+        const int tn = min(DMIN_TILE, c1 - t0);
+        __syncthreads();
+        stage_points<MOVING>(lds, pts, t0, tn);
+        __syncthreads();
+        int i = 0;
+        for (; i + 2 <= tn; i += 2) {
+            float dx0, dy0, dx1, dy1, m0, m1;
+            bool o0, o1;
+            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
+            point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
+            F.eval(dx0, dy0, m0, o0);
+            F.eval(dx1, dy1, m1, o1);
+            best = fminf(best, fminf(pair_combine(m0, o0), pair_combine(m1, o1)));
+        }
+        if (i < tn) {
+            float dx, dy, m;
+            bool o;
+            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
+            F.eval(dx, dy, m, o);
+            best = fminf(best, pair_combine(m, o));
         }
     }
 }

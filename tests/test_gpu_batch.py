@@ -20,8 +20,9 @@ def pkg():
 
 
 def _mixed_scenes():
-    """Six small scenes covering every register class, moving points, all
-    motion models and a scene without validation."""
+    """Seven small scenes covering every register class (large polygons with
+    static and with moving points), all motion models and a scene without
+    validation."""
     out = []
     p1, s1 = scenes.config("c1", K=192, T=12)
     out.append((p1, s1))
@@ -44,6 +45,10 @@ def _mixed_scenes():
                        u_max=(0.6,))
     out.append((p6, dict(ox=pts[:50, 0].copy(), oy=pts[:50, 1].copy(), polygon=scenes.FOOTPRINT_L8,
                          rects=None, valid=(np.arange(50) % 3 != 0).astype(np.uint8))))
+    V19 = scenes.star_polygon(rng, 19)
+    p7 = scenes.params("c3", K=96, T=7, footprint_kind=0, goal=(2.0, -1.0))
+    s7 = {k: (v[:1800] if isinstance(v, np.ndarray) and v.ndim == 1 else v) for k, v in s3.items()}
+    out.append((p7, dict(s7, polygon=V19, rects=None)))
     return out
 
 
