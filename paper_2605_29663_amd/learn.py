@@ -10,11 +10,14 @@ forward / backward passes, Adam); this module only orchestrates them.
   held (invalid) steps carry no target and are skipped.  Sample = (features
   of the state before the step, updated nominal scaled to [-1, 1]).
 * Training: minibatch Adam on the mean squared error.
-* Evaluation: for held-out states, one MPPI update from (a) the plain shifted
-  nominal with K = 4096, (b) the same with K = 1024, (c) the network's mean
-  with K = 1024 (falling back to the shifted nominal when the mean's
-  noise-free cost is higher); the score of an update is the noise-free
-  augmented cost of the updated nominal (a K = 1, sigma = 0 rollout).
+* Evaluation: for held-out states, repeated MPPI updates (independent noise)
+  from (a) the plain shifted nominal with K = 4096, (b) the same with
+  K = 1024, (c) the network's mean with K = 1024 (falling back to the shifted
+  nominal when the mean's noise-free cost is higher); the score of an update
+  is the noise-free cost of the updated nominal, J_nom, which carries the
+  w_inf penalty when the update fails validation.  Ratios are taken over the
+  states where every method validated; penalised fractions are reported
+  separately.
 """
 from __future__ import annotations
 
@@ -147,9 +150,15 @@ def nominal_cost(ctx, prm, q, U):
 
 
 def evaluate(net, n_states=1000, n_parallel=64, warm_steps=40, seed0=HELDOUT_SEED0,
-             K_big=4096, K_small=1024, log=print):
-    """Held-out comparison; returns per-state costs (plain_big, plain_small, learned)."""
-    rows = []
+             K_big=4096, K_small=1024, repeats=4, log=print):
+    """Held-out comparison.  For each state, `repeats` independent updates of
+    each method (different noise seeds): (a) plain from the shifted nominal,
+    K_big; (b) the same with K_small; (c) from the network's mean with
+    K_small (the shifted nominal when the mean's noise-free cost is higher).
+    The score of an update is the noise-free cost J_nom of the updated
+    nominal (+ w_inf when it fails validation).  Returns (costs (n, 3):
+    per-state means over the repeats, fallback flags (n,))."""
+    rows, fallback = [], []
     ep = 0
     t0 = time.time()
     while len(rows) < n_states:
@@ -165,43 +174,59 @@ def evaluate(net, n_states=1000, n_parallel=64, warm_steps=40, seed0=HELDOUT_SEE
                     break
                 ctx, p = E.ctxs[s], E.prms[s]
                 q = qb[s]
-                seed = int(seed0 + 7919 * len(rows))
-                # (a), (b): plain updates from the shifted nominal
-                res = []
-                for K in (K_big, K_small):
-                    U = Ub[s].clone().contiguous()
-                    _, _, D = ctx.mppi_step(dict(p, K=K, validate=0), q, U, seed, 0, diag=True)
-                    res.append(nominal_cost(ctx, p, q, D["U_upd"]))
-                # (c): learned mean, fallback to the shifted nominal
                 net.set_scaling(p)
                 f = net.features(ctx, torch.tensor(q[None], device="cuda"), Ub[s:s + 1])
                 mu = net.mean(f)[0].contiguous()
-                if nominal_cost(ctx, p, q, mu) > nominal_cost(ctx, p, q, Ub[s]):
+                fb = nominal_cost(ctx, p, q, mu) > nominal_cost(ctx, p, q, Ub[s])
+                if fb:
                     mu = Ub[s].clone().contiguous()
-                _, _, D = ctx.mppi_step(dict(p, K=K_small, validate=0), q, mu, seed, 0, diag=True)
-                res.append(nominal_cost(ctx, p, q, D["U_upd"]))
+                res = np.zeros(3)
+                for r in range(repeats):
+                    seed = int(seed0 + 7919 * len(rows) + 104729 * r)
+                    for j, (K, U0) in enumerate(((K_big, Ub[s]), (K_small, Ub[s]), (K_small, mu))):
+                        U = U0.clone().contiguous()
+                        _, _, D = ctx.mppi_step(dict(p, K=K, validate=1), q, U, seed, 0, diag=True)
+                        res[j] += float(D["J_nom"][0].item()) / repeats
                 rows.append(res)
+                fallback.append(bool(fb))
             log(f"evaluate: {len(rows)} states, {time.time() - t0:.0f} s")
         E.batch.close()
         ep += 1
-    return np.array(rows)
+    return np.array(rows), np.array(fallback)
 
 
-def summarize(costs, seed=0, n_boot=2000):
-    """Mean cost ratios learned / plain@big and plain@small / plain@big, with
-    bootstrap 95 % intervals, and learned / plain@small (the gain at equal K)."""
+def summarize(costs, fallback=None, w_inf=1e4, seed=0, n_boot=2000):
+    """Final-cost ratios learned@K_small / plain@K_big, plain@K_small /
+    plain@K_big and learned / plain at equal K: ratio of means over the
+    states where every method's updates validated (the costs there are free
+    of the w_inf penalty), with bootstrap 95 % intervals over states; the
+    median of the per-state ratios; and how often each method failed
+    validation on average."""
     rng = np.random.default_rng(seed)
-    big, small, learned = costs[:, 0], costs[:, 1], costs[:, 2]
+    costs = np.asarray(costs, dtype=np.float64)
+    feas = np.all(costs < 0.5 * w_inf, axis=1)
+    c = costs[feas]
+    big, small, learned = c[:, 0], c[:, 1], c[:, 2]
 
     def ratio(a, b):
+        if a.size == 0:
+            return {"ratio": None, "ci95": [None, None], "median_state_ratio": None}
         r = float(a.mean() / b.mean())
         idx = rng.integers(0, len(a), (n_boot, len(a)))
         bs = a[idx].mean(1) / b[idx].mean(1)
-        return {"ratio": r, "ci95": [float(np.percentile(bs, 2.5)), float(np.percentile(bs, 97.5))]}
+        return {"ratio": r, "ci95": [float(np.percentile(bs, 2.5)), float(np.percentile(bs, 97.5))],
+                "median_state_ratio": float(np.median(a / b))}
 
-    return {"n_states": int(len(costs)),
-            "learned_small_over_plain_big": ratio(learned, big),
-            "plain_small_over_plain_big": ratio(small, big),
-            "learned_small_over_plain_small": ratio(learned, small),
-            "mean_cost": {"plain_big": float(big.mean()), "plain_small": float(small.mean()),
-                          "learned_small": float(learned.mean())}}
+    out = {"n_states": int(len(costs)), "n_feasible": int(feas.sum()),
+           "learned_small_over_plain_big": ratio(learned, big),
+           "plain_small_over_plain_big": ratio(small, big),
+           "learned_small_over_plain_small": ratio(learned, small),
+           "mean_cost_feasible": {"plain_big": float(big.mean()) if big.size else None,
+                                  "plain_small": float(small.mean()) if small.size else None,
+                                  "learned_small": float(learned.mean()) if learned.size else None},
+           "mean_penalised_fraction": {"plain_big": float(np.mean(costs[:, 0] >= 0.5 * w_inf)),
+                                       "plain_small": float(np.mean(costs[:, 1] >= 0.5 * w_inf)),
+                                       "learned_small": float(np.mean(costs[:, 2] >= 0.5 * w_inf))}}
+    if fallback is not None:
+        out["fallback_fraction"] = float(np.mean(fallback))
+    return out

@@ -23,6 +23,9 @@ def main():
     ap.add_argument("--out", default=".")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-data-seconds", type=float, default=420.0)
+    ap.add_argument("--eval-only", default=None,
+                    help="skip data and training: evaluate the weights in this file")
+    ap.add_argument("--repeats", type=int, default=4)
     args = ap.parse_args()
     import torch
     import paper_2605_29663_amd as pkg
@@ -34,22 +37,31 @@ def main():
     os.makedirs(args.out, exist_ok=True)
     t0 = time.time()
     net = pkg.Proposal(40, 2, hidden=256, max_batch=1024)
-    X, Y = learn.generate(args.samples, n_parallel=args.parallel, net=net, log=log,
-                          max_seconds=args.max_data_seconds)
-    log(f"data: {X.shape[0]} samples in {time.time() - t0:.0f} s")
-    net.init_params(args.seed)
-    t1 = time.time()
-    losses = learn.train(net, X, Y, epochs=args.epochs, log=log)
-    log(f"train: {time.time() - t1:.0f} s, final loss {losses[-1]:.5f}")
-    net.save(os.path.join(args.out, "proposal_c2.bin"))
-    t2 = time.time()
-    costs = learn.evaluate(net, n_states=args.eval_states, n_parallel=args.parallel, log=log)
-    summary = learn.summarize(costs)
-    summary.update(samples=int(X.shape[0]), epochs=args.epochs, train_loss=losses,
+    if args.eval_only:
+        net.load(args.eval_only)
+        n_samples, losses = None, None
+        t1 = t2 = time.time()
+    else:
+        X, Y = learn.generate(args.samples, n_parallel=args.parallel, net=net, log=log,
+                              max_seconds=args.max_data_seconds)
+        n_samples = int(X.shape[0])
+        log(f"data: {n_samples} samples in {time.time() - t0:.0f} s")
+        net.init_params(args.seed)
+        t1 = time.time()
+        losses = learn.train(net, X, Y, epochs=args.epochs, log=log)
+        log(f"train: {time.time() - t1:.0f} s, final loss {losses[-1]:.5f}")
+        net.save(os.path.join(args.out, "proposal_c2.bin"))
+        t2 = time.time()
+    costs, fallback = learn.evaluate(net, n_states=args.eval_states, n_parallel=args.parallel,
+                                     repeats=args.repeats, log=log)
+    summary = learn.summarize(costs, fallback)
+    summary.update(samples=n_samples, epochs=args.epochs, train_loss=losses, repeats=args.repeats,
+                   per_state_costs=costs.tolist(), fallback=fallback.tolist(),
                    seconds={"data": t1 - t0, "train": t2 - t1, "eval": time.time() - t2})
     with open(os.path.join(args.out, "proposal_c2_eval.json"), "w") as f:
         json.dump(summary, f, indent=1)
-    log(json.dumps({k: v for k, v in summary.items() if k != "train_loss"}))
+    log(json.dumps({k: v for k, v in summary.items()
+                    if k not in ("train_loss", "per_state_costs", "fallback")}))
 
 
 if __name__ == "__main__":

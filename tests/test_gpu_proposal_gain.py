@@ -1,0 +1,39 @@
+"""What the trained proposal gains: on held-out corridor states (seeds
+disjoint from training), one MPPI update at K = 1024 around the network's
+mean (with the plain shifted nominal as fallback) against the same update
+around the plain shifted nominal at K = 1024 and at K = 4096, scored by the
+noise-free cost of the updated nominal.  Uses the shipped weights, trained
+on the GPU by the library's own kernels (paper_2605_29663_amd.train_proposal)."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2605_29663_amd", "proposal_c2.bin")
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_29663_amd as p
+    p.load()
+    return p
+
+
+def test_trained_proposal_beats_plain_at_equal_rollouts(pkg):
+    from paper_2605_29663_amd import learn
+    assert os.path.exists(WEIGHTS)
+    net = pkg.Proposal(40, 2, hidden=256, max_batch=64)
+    net.load(WEIGHTS)
+    costs, fallback = learn.evaluate(net, n_states=96, n_parallel=16, warm_steps=20, repeats=2,
+                                     seed0=learn.HELDOUT_SEED0 + 500000, log=lambda m: None)
+    s = learn.summarize(costs, fallback, n_boot=500)
+    print(s)
+    gain = s["learned_small_over_plain_small"]["ratio"]
+    # the learned mean lowers the final cost at the same number of rollouts
+    assert gain < 1.0, s
