@@ -453,11 +453,21 @@ MPPI_API int proposal_features(mppi_proposal p, mppi_ctx ctx, const float* dq0,
                                const float* dU_prev, int M, float* dfeat);
 /* Network output (scaled units, device M x T*nu) of M feature rows.        */
 MPPI_API int proposal_forward(mppi_proposal p, const float* dfeat, int M, float* dout);
+/* Output mode.  scale = 0 (default): the output y is the sequence in
+ * scaled units, u = mid + half y.  scale > 0 (residual mode): the output is
+ * a correction of the previous sequence carried in the features,
+ * u = mid + half (u_prev_scaled + scale y), so the network only encodes the
+ * update (bf16 operands then round the correction, not the sequence).
+ * Saved with the weights.                                                   */
+MPPI_API int proposal_set_residual(mppi_proposal p, float scale);
 /* Sampling mean: the output mapped back into the control box (device
  * M x T x nu), ready to be the nominal of mppi_step.                        */
 MPPI_API int proposal_mean(mppi_proposal p, const float* dfeat, int M, float* dU);
-/* Control sequences (device M x T x nu) -> scaled training targets.         */
-MPPI_API int proposal_normalize(mppi_proposal p, const float* dU, int M, float* dtarget);
+/* Control sequences (device M x T x nu) -> training targets in the output's
+ * units; dfeat (device M x in_dim, the features of the same states) is
+ * needed in residual mode and may be NULL otherwise.                        */
+MPPI_API int proposal_normalize(mppi_proposal p, const float* dU, const float* dfeat, int M,
+                                float* dtarget);
 /* One Adam step on the mean squared error of M rows (dfeat, dtarget device;
  * targets in scaled units).  loss_out (host, may be NULL) receives the loss
  * of the forward pass before the update (synchronous when given).          */

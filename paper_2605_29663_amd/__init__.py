@@ -38,6 +38,7 @@ EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footpri
            "proposal_create", "proposal_destroy", "proposal_last_error", "proposal_num_params",
            "proposal_shape", "proposal_set_params", "proposal_get_params", "proposal_set_scaling",
            "proposal_features", "proposal_forward", "proposal_mean", "proposal_normalize",
+           "proposal_set_residual",
            "proposal_train_step", "proposal_get_buffer", "proposal_save", "proposal_load")
 
 
@@ -158,7 +159,8 @@ def load():
     L.proposal_features.argtypes = [vp, vp, vp, vp, i, vp]
     L.proposal_forward.argtypes = [vp, vp, i, vp]
     L.proposal_mean.argtypes = [vp, vp, i, vp]
-    L.proposal_normalize.argtypes = [vp, vp, i, vp]
+    L.proposal_normalize.argtypes = [vp, vp, vp, i, vp]
+    L.proposal_set_residual.argtypes = [vp, f]
     L.proposal_train_step.argtypes = [vp, vp, vp, i, f, ctypes.POINTER(f)]
     L.proposal_get_buffer.argtypes = [vp, i, vp, ll]
     L.proposal_save.argtypes = [vp, ctypes.c_char_p]
@@ -636,12 +638,20 @@ class Proposal:
         self._check(self.lib.proposal_mean(self.h, _ptr(feat), feat.shape[0], _ptr(U)))
         return U
 
-    def normalize(self, U):
+    def normalize(self, U, feat=None):
+        """Training targets of the sequences U; feat (the same states'
+        features) is needed in residual mode."""
         U = _dev_f32(U, self.device, "U")
         M = U.numel() // (self.T * self.nu)
+        if feat is not None:
+            feat = _dev_f32(feat, self.device, "feat")
         y = torch.empty((M, self.out_dim), dtype=torch.float32, device=self.device)
-        self._check(self.lib.proposal_normalize(self.h, _ptr(U), M, _ptr(y)))
+        self._check(self.lib.proposal_normalize(self.h, _ptr(U), _ptr(feat), M, _ptr(y)))
         return y
+
+    def set_residual(self, scale):
+        """0: outputs are sequences; > 0: corrections of the previous sequence."""
+        self._check(self.lib.proposal_set_residual(self.h, float(scale)))
 
     def train_step(self, feat, target, lr, want_loss=True):
         feat = _dev_f32(feat, self.device, "feat")

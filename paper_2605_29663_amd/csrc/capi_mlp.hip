@@ -255,15 +255,23 @@ int proposal_mean(mppi_proposal p, const float* dfeat, int M, float* dU) {
     if (int rc = check_batch(p, M)) return rc;
     DeviceGuard g(p->device);
     if (int rc = forward(p, dfeat, M)) return rc;
-    PHIP(p, launch_denorm(p->outb.as<float>(), M, p->T, p->nu, p->F, dU, p->stream));
+    PHIP(p, launch_denorm(p->outb.as<float>(), dfeat, M, p->T, p->nu, p->F, dU, p->stream));
     return MPPI_OK;
 }
 
-int proposal_normalize(mppi_proposal p, const float* dU, int M, float* dtarget) {
+int proposal_normalize(mppi_proposal p, const float* dU, const float* dfeat, int M, float* dtarget) {
     if (!p || !dU || !dtarget) return MPPI_E_ARG;
     if (M < 1) return pfail(p, MPPI_E_ARG, "M < 1");
+    if (p->F.res_scale > 0.0f && !dfeat) return pfail(p, MPPI_E_ARG, "residual targets need the features");
     DeviceGuard g(p->device);
-    PHIP(p, launch_normalize(dU, M, p->T, p->nu, p->F, dtarget, p->stream));
+    PHIP(p, launch_normalize(dU, dfeat, M, p->T, p->nu, p->F, dtarget, p->stream));
+    return MPPI_OK;
+}
+
+int proposal_set_residual(mppi_proposal p, float scale) {
+    if (!p) return MPPI_E_ARG;
+    if (!(scale >= 0.0f) || !std::isfinite(scale)) return pfail(p, MPPI_E_ARG, "scale must be >= 0");
+    p->F.res_scale = scale;
     return MPPI_OK;
 }
 
@@ -351,7 +359,7 @@ int proposal_save(mppi_proposal p, const char* path) {
     PHIP(p, hipStreamSynchronize(p->stream));
     FILE* f = std::fopen(path, "wb");
     if (!f) return pfail(p, MPPI_E_ARG, "cannot open %s", path);
-    const int hdr[6] = {0x50494d45, p->in, p->H, p->out, p->T, p->nu};  // "EMIP"
+    const int hdr[6] = {0x50494d46, p->in, p->H, p->out, p->T, p->nu};  // "EMIP"
     bool ok = std::fwrite(hdr, sizeof hdr, 1, f) == 1 && std::fwrite(&p->t, sizeof p->t, 1, f) == 1 &&
               std::fwrite(&p->F, sizeof p->F, 1, f) == 1 &&
               std::fwrite(w.data(), 4, w.size(), f) == w.size() &&
@@ -369,7 +377,7 @@ int proposal_load(mppi_proposal p, const char* path) {
     long long t = 0;
     FeatArgs F;
     std::vector<float> w(p->n_params), m(p->n_params), v(p->n_params);
-    bool ok = std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 0x50494d45 && hdr[1] == p->in &&
+    bool ok = std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 0x50494d46 && hdr[1] == p->in &&
               hdr[2] == p->H && hdr[3] == p->out && std::fread(&t, sizeof t, 1, f) == 1 &&
               std::fread(&F, sizeof F, 1, f) == 1 && std::fread(w.data(), 4, w.size(), f) == w.size() &&
               std::fread(m.data(), 4, m.size(), f) == m.size() &&

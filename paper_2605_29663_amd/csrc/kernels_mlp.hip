@@ -242,34 +242,45 @@ __global__ void k_f32_to_bf16(const float* __restrict__ src, uint16_t* __restric
 
 // Normalised network output -> control sequence in the actuator box:
 // u = clamp(mid + half * y, u_min, u_max) per channel.
-__global__ void k_denorm(const float* __restrict__ y, int M, int T, int nu, FeatArgs F,
-                         float* __restrict__ U) {
+// In residual mode (res_scale > 0) the output is added to the previous
+// sequence's scaled value carried in the features: ys = feat_U + res_scale y.
+__global__ void k_denorm(const float* __restrict__ y, const float* __restrict__ feat, int M, int T,
+                         int nu, FeatArgs F, float* __restrict__ U) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M * T * nu) return;
     const int ch = i % nu;
+    const int m = i / (T * nu), k = i % (T * nu);
+    const float ys = F.res_scale > 0.0f
+                         ? __builtin_fmaf(F.res_scale, y[i], feat[static_cast<size_t>(m) * F.in_dim + FEAT_BINS + 2 + k])
+                         : y[i];
     const float mid = (F.umax[ch] + F.umin[ch]) * 0.5f;
     const float half = (F.umax[ch] - F.umin[ch]) * 0.5f;
-    U[i] = fminf(fmaxf(mid + half * y[i], F.umin[ch]), F.umax[ch]);
+    U[i] = fminf(fmaxf(mid + half * ys, F.umin[ch]), F.umax[ch]);
 }
 
 // Control sequences -> normalised training targets: y = (u - mid) / half.
-__global__ void k_normalize(const float* __restrict__ U, int M, int T, int nu, FeatArgs F,
-                            float* __restrict__ y) {
+// (residual mode: y = (ys - feat_U) / res_scale)
+__global__ void k_normalize(const float* __restrict__ U, const float* __restrict__ feat, int M,
+                            int T, int nu, FeatArgs F, float* __restrict__ y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M * T * nu) return;
     const int ch = i % nu;
+    const int m = i / (T * nu), k = i % (T * nu);
     const float mid = (F.umax[ch] + F.umin[ch]) * 0.5f;
     const float half = (F.umax[ch] - F.umin[ch]) * 0.5f;
-    y[i] = half > 0.0f ? (U[i] - mid) / half : 0.0f;
+    const float ys = half > 0.0f ? (U[i] - mid) / half : 0.0f;
+    y[i] = F.res_scale > 0.0f
+               ? (ys - feat[static_cast<size_t>(m) * F.in_dim + FEAT_BINS + 2 + k]) / F.res_scale
+               : ys;
 }
 
 }  // namespace
 
-hipError_t launch_normalize(const float* U, int M, int T, int nu, const FeatArgs& F, float* y,
-                            hipStream_t s) {
+hipError_t launch_normalize(const float* U, const float* feat, int M, int T, int nu,
+                            const FeatArgs& F, float* y, hipStream_t s) {
     const int n = M * T * nu;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_normalize, dim3((n + 255) / 256), dim3(256), 0, s, U, M, T, nu, F, y);
+    hipLaunchKernelGGL(k_normalize, dim3((n + 255) / 256), dim3(256), 0, s, U, feat, M, T, nu, F, y);
     return hipGetLastError();
 }
 
@@ -323,11 +334,11 @@ hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, long n, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_denorm(const float* y, int M, int T, int nu, const FeatArgs& F, float* U,
-                         hipStream_t s) {
+hipError_t launch_denorm(const float* y, const float* feat, int M, int T, int nu, const FeatArgs& F,
+                         float* U, hipStream_t s) {
     const int n = M * T * nu;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_denorm, dim3((n + 255) / 256), dim3(256), 0, s, y, M, T, nu, F, U);
+    hipLaunchKernelGGL(k_denorm, dim3((n + 255) / 256), dim3(256), 0, s, y, feat, M, T, nu, F, U);
     return hipGetLastError();
 }
 

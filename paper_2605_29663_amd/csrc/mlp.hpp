@@ -15,6 +15,7 @@ struct FeatArgs {
     float r_max;             // histogram range clip (m); also scales the goal
     float goal[2];
     float umin[3], umax[3];  // control box: features and outputs use (u - mid) / half
+    float res_scale;         // > 0: the output is a residual on the previous sequence
 };
 
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
@@ -52,9 +53,9 @@ hipError_t launch_colsum(const float* d, int M, int N, float* out, hipStream_t s
 hipError_t launch_adam(float* w, const float* grad, float* m, float* v, long n, const AdamArgs& a,
                        hipStream_t s);
 hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, long n, hipStream_t s);
-hipError_t launch_normalize(const float* U, int M, int T, int nu, const FeatArgs& F, float* y,
+hipError_t launch_normalize(const float* U, const float* feat, int M, int T, int nu, const FeatArgs& F, float* y,
                             hipStream_t s);
-hipError_t launch_denorm(const float* y, int M, int T, int nu, const FeatArgs& F, float* U,
+hipError_t launch_denorm(const float* y, const float* feat, int M, int T, int nu, const FeatArgs& F, float* U,
                          hipStream_t s);
 
 }  // namespace emppi

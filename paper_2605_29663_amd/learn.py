@@ -8,7 +8,10 @@ forward / backward passes, Adam); this module only orchestrates them.
   batched step.  For a validated step the updated nominal is recovered exactly
   from its outputs (u* = U_upd[0], and the shifted nominal holds U_upd[1:]);
   held (invalid) steps carry no target and are skipped.  Sample = (features
-  of the state before the step, updated nominal scaled to [-1, 1]).
+  of the state before the step, updated nominal).
+* Targets: by default the residual form, the correction of the previous
+  sequence in units of its rms size over the data (the network then encodes
+  only the update; see proposal_set_residual).
 * Training: minibatch Adam on the mean squared error.
 * Evaluation: for held-out states, repeated MPPI updates (independent noise)
   from (a) the plain shifted nominal with K = 4096, (b) the same with
@@ -89,8 +92,8 @@ class Episodes:
 
 def generate(n_samples, n_parallel=64, steps_per_episode=200, K=4096, seed0=TRAIN_SEED0,
              net=None, log=print, max_seconds=None):
-    """Features and scaled targets of (up to) n_samples validated plain-MPPI steps,
-    stopping early after max_seconds."""
+    """Features and updated nominals (M x T*nu, control units) of (up to)
+    n_samples validated plain-MPPI steps, stopping early after max_seconds."""
     T = 40
     if net is None:
         net = pkg.Proposal(T, 2, hidden=256, max_batch=1024)
@@ -106,7 +109,7 @@ def generate(n_samples, n_parallel=64, steps_per_episode=200, K=4096, seed0=TRAI
                 f = net.features(E.ctxs[s], torch.tensor(qb[s:s + 1], device="cuda"), Ub[s:s + 1])
                 U_upd = torch.cat([torch.tensor(u[s:s + 1, :2], device="cuda"), Ua[s, :-1]], 0)
                 feats.append(f)
-                targets.append(net.normalize(U_upd.contiguous()))
+                targets.append(U_upd.reshape(1, -1))
             have += int(valid.sum())
             if have >= n_samples or (max_seconds and time.time() - t0 > max_seconds):
                 break
@@ -119,6 +122,19 @@ def generate(n_samples, n_parallel=64, steps_per_episode=200, K=4096, seed0=TRAI
     X = torch.cat(feats)[:n_samples].contiguous()
     Y = torch.cat(targets)[:n_samples].contiguous()
     return X, Y
+
+
+def make_targets(net, X, U_upd, residual=True):
+    """Training targets of the updated nominals.  Residual mode: the output
+    is the correction of the previous sequence (the features' last T*nu
+    entries) in units of its root-mean-square size over the data set."""
+    net.set_residual(0.0)
+    if not residual:
+        return net.normalize(U_upd), 0.0
+    y_abs = net.normalize(U_upd)
+    scale = float((y_abs - X[:, X.shape[1] - y_abs.shape[1]:]).pow(2).mean().sqrt())
+    net.set_residual(scale)
+    return net.normalize(U_upd, X), scale
 
 
 def train(net, X, Y, epochs=30, batch=1024, lr=1e-3, lr_final=1e-4, seed=0, log=print):

@@ -26,6 +26,8 @@ def main():
     ap.add_argument("--eval-only", default=None,
                     help="skip data and training: evaluate the weights in this file")
     ap.add_argument("--repeats", type=int, default=4)
+    ap.add_argument("--absolute", action="store_true",
+                    help="train on absolute sequences instead of residual corrections")
     args = ap.parse_args()
     import torch
     import paper_2605_29663_amd as pkg
@@ -42,10 +44,12 @@ def main():
         n_samples, losses = None, None
         t1 = t2 = time.time()
     else:
-        X, Y = learn.generate(args.samples, n_parallel=args.parallel, net=net, log=log,
-                              max_seconds=args.max_data_seconds)
+        X, U_upd = learn.generate(args.samples, n_parallel=args.parallel, net=net, log=log,
+                                  max_seconds=args.max_data_seconds)
         n_samples = int(X.shape[0])
         log(f"data: {n_samples} samples in {time.time() - t0:.0f} s")
+        Y, scale = learn.make_targets(net, X, U_upd, residual=not args.absolute)
+        log(f"targets: residual scale {scale:.5f}")
         net.init_params(args.seed)
         t1 = time.time()
         losses = learn.train(net, X, Y, epochs=args.epochs, log=log)

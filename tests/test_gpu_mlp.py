@@ -166,3 +166,38 @@ def test_features_bit_exact(pkg, orc):
     yn = net.normalize(torch.tensor(U, device="cuda")).cpu().numpy()
     np.testing.assert_allclose(yn.reshape(U.shape), (U - (hi + lo) / 2) / ((hi - lo) / 2), rtol=1e-6,
                                atol=1e-7)
+
+
+def test_residual_mode_mean_and_targets(pkg):
+    """Residual mode: the mean is the previous sequence (from the features)
+    plus scale x output, in the control box; targets invert it."""
+    import torch
+    prm, sc = scenes.config("c2")
+    ctx = pkg.Context(0)
+    ctx.set_footprint(pkg.POLYGON, sc["polygon"])
+    ctx.set_points(sc["ox"], sc["oy"])
+    net = pkg.Proposal(prm["T"], prm["nu"], hidden=H, max_batch=64)
+    net.init_params(3)
+    net.set_scaling(prm)
+    rng = np.random.default_rng(8)
+    M = 7
+    q0 = np.concatenate([rng.uniform(-1, 4, (M, 2)), rng.uniform(-3, 3, (M, 1))], 1).astype(np.float32)
+    U = rng.uniform(-1.2, 1.2, (M, prm["T"], 2)).astype(np.float32)
+    f = net.features(ctx, torch.tensor(q0, device="cuda"), torch.tensor(U, device="cuda"))
+    y = net.forward(f).cpu().numpy().reshape(M, prm["T"], 2)
+    s = 0.07
+    net.set_residual(s)
+    Um = net.mean(f).cpu().numpy()
+    lo, hi = np.float32(prm["u_min"]), np.float32(prm["u_max"])
+    mid, half = (hi + lo) / 2, (hi - lo) / 2
+    prev = f.cpu().numpy()[:, 66:].reshape(M, prm["T"], 2)
+    ref = np.clip(mid + half * (prev + s * y), lo, hi)
+    np.testing.assert_allclose(Um, ref, rtol=1e-6, atol=1e-6)
+    Ut = np.clip(U + 0.05 * rng.standard_normal(U.shape).astype(np.float32), lo, hi)
+    t = net.normalize(torch.tensor(Ut, device="cuda"), f).cpu().numpy().reshape(M, prm["T"], 2)
+    np.testing.assert_allclose(t, ((Ut - mid) / half - prev) / s, rtol=1e-5, atol=1e-4)
+    with pytest.raises(pkg.MppiError):
+        net.normalize(torch.tensor(Ut, device="cuda"))       # residual targets need features
+    net.set_residual(0.0)
+    np.testing.assert_allclose(net.mean(f).cpu().numpy(), np.clip(mid + half * y, lo, hi),
+                               rtol=1e-6, atol=1e-6)
