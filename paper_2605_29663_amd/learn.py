@@ -231,7 +231,10 @@ def summarize(costs, fallback=None, w_inf=1e4, seed=0, n_boot=2000):
         idx = rng.integers(0, len(a), (n_boot, len(a)))
         bs = a[idx].mean(1) / b[idx].mean(1)
         return {"ratio": r, "ci95": [float(np.percentile(bs, 2.5)), float(np.percentile(bs, 97.5))],
-                "median_state_ratio": float(np.median(a / b))}
+                "median_state_ratio": float(np.median(a / b)),
+                # paired per-state comparison (sign-test counts)
+                "states_lower": int(np.sum(a < b)), "states_equal": int(np.sum(a == b)),
+                "states_higher": int(np.sum(a > b))}
 
     out = {"n_states": int(len(costs)), "n_feasible": int(feas.sum()),
            "learned_small_over_plain_big": ratio(learned, big),
