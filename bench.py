@@ -18,6 +18,7 @@ CPU oracle timed on a bounded sample of the same step.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -43,9 +44,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "hybrid", "cloud"],
+    ap.add_argument("--config", default="c2",
+                    choices=["c1", "c2", "c3", "c4", "hybrid", "cloud", "exp1"],
                     help="c1/c2/c3: single-scene step; c4: 64-scene batched step (graph); "
-                         "hybrid: three-mode cycle (Algorithm 2); cloud: point-cloud downsampling")
+                         "hybrid: three-mode cycle (Algorithm 2); cloud: point-cloud downsampling; "
+                         "exp1: point-wise polygon vs rectangle-cover evaluator (L, T, F shapes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the tile shapes instead of using the shipped table")
@@ -181,6 +184,54 @@ def run_cloud(args):
     ctx.close()
 
 
+def run_exp1(args):
+    """Point-wise evaluator timing in the shape of the paper's Experiment 1:
+    query points uniform in a 50 x 50 m square, 1e2 .. 1e6 per call, the L, T
+    and F footprints as polygons and as rectangle covers."""
+    import numpy as np
+    import torch
+    import paper_2605_29663_amd as pkg
+    from paper_2605_29663_amd import scenes
+
+    ctx = pkg.Context(0)
+    lib = ctx.lib
+    stream = torch.cuda.current_stream()
+    rows = []
+    for name, (poly, rects) in scenes.SHAPES_LTF.items():
+        ctx.set_footprint(pkg.POLYGON, poly)
+        ctx.set_footprint(pkg.RECTS, rects)
+        for n in (100, 1000, 10000, 100000, 1000000):
+            rng = np.random.default_rng(n)
+            p = torch.tensor(rng.uniform(-25, 25, (2, n)).astype(np.float32), device="cuda")
+            out = torch.empty(n, dtype=torch.float32, device="cuda")
+            res = {}
+            for kind, fn in (("polygon", lib.sdf_polygon), ("rect_cover", lib.sdf_rectcover)):
+                args_c = (ctx.h, ctypes.c_void_p(p[0].data_ptr()), ctypes.c_void_p(p[1].data_ptr()),
+                          n, ctypes.c_void_p(out.data_ptr()))
+                for _ in range(max(3, args.warmup)):
+                    fn(*args_c)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = max(20, args.steps)
+                e0.record(stream)
+                for _ in range(reps):
+                    fn(*args_c)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                res[kind] = e0.elapsed_time(e1) * 1e3 / reps      # us per call
+            rows.append({"shape": name, "points": n, "B": len(poly), "R": len(rects),
+                         "polygon_us": res["polygon"], "rect_cover_us": res["rect_cover"],
+                         "polygon_over_rect": res["polygon"] / res["rect_cover"]})
+    ref = {r["shape"]: r for r in rows if r["points"] == 100000}
+    print(json.dumps({
+        "metric": "point-wise signed-distance evaluation time per call", "unit": "us",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+        "data": "synthetic (query points uniform in a 50 x 50 m square)",
+        "config": {"workload": "evaluator calls, L/T/F footprints, 1e2..1e6 points"},
+        "polygon_over_rect_at_1e5": {k: v["polygon_over_rect"] for k, v in ref.items()},
+        "rows": rows}))
+    ctx.close()
+
+
 def run_batched(args):
     """64 uneven scenes in one batched step, replayed from the captured graph."""
     import numpy as np
@@ -272,6 +323,9 @@ def main():
         return
     if args.config == "cloud":
         run_cloud(args)
+        return
+    if args.config == "exp1":
+        run_exp1(args)
         return
     import numpy as np
     import torch

@@ -79,6 +79,7 @@ struct mppi_ctx_s {
     DevBuf cloud_keys, cloud_first, cloud_cell, cloud_r2, cloud_flag, cloud_excl, cloud_misc;
     // step workspaces
     DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom, out;
+    DevBuf sync_ctr;  // last-workgroup counters of the fused launches (0 between launches)
     float* h_out = nullptr;  // pinned
     // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
     std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
@@ -304,11 +305,10 @@ inline void choose_tiles(int kind, int padded, int npose, int n_points, int& blo
     nchunk = std::max(1, (n_points + chunk - 1) / chunk);
 }
 
-// Fused transform + signed distance + min launch; the keys (key, or key64
-// when argmin) must hold their initial values for the poses.
-inline int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind,
-                    unsigned int* key, unsigned long long* key64, int force_block = 0,
-                    int force_nchunk = 0) {
+// Launch shape of the fused transform + signed distance + min stage.
+inline DminLaunch dmin_launch(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind,
+                              unsigned int* key, unsigned long long* key64, int force_block = 0,
+                              int force_nchunk = 0) {
     const int padded = kind == 0 ? ctx->BP : ctx->RP;
     int block, nchunk, chunk;
     choose_tiles(kind, padded, npose, ctx->n_points, block, nchunk, chunk);
@@ -340,6 +340,15 @@ inline int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, i
     L.argmin = key64 != nullptr;
     L.key = key;
     L.key64 = key64;
+    return L;
+}
+
+// Fused transform + signed distance + min launch; the keys (key, or key64
+// when argmin) must hold their initial values for the poses.
+inline int run_dmin(mppi_ctx ctx, const float4* poses, int npose, PoseTime pt, int kind,
+                    unsigned int* key, unsigned long long* key64, int force_block = 0,
+                    int force_nchunk = 0) {
+    const DminLaunch L = dmin_launch(ctx, poses, npose, pt, kind, key, key64, force_block, force_nchunk);
     HIP_TRY(ctx, launch_dmin(L, ctx->stream));
     return MPPI_OK;
 }
