@@ -37,8 +37,6 @@ int mppi_create(mppi_ctx* out, int device, void* hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard g(device);
     e = ctx->n_valid.ensure(sizeof(int));
-    if (e == hipSuccess) e = ctx->sync_ctr.ensure(4 * sizeof(int));
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->sync_ctr.p, 0, 4 * sizeof(int), ctx->stream);
     if (e == hipSuccess) e = ctx->path.ensure(MPPI_MAX_PATH * sizeof(float2));
     if (e == hipSuccess) e = ctx->out.ensure(OUT_FLOATS * sizeof(float));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_out), OUT_FLOATS * sizeof(float), 0);
@@ -60,7 +58,7 @@ int mppi_destroy(mppi_ctx ctx) {
         if (ctx->gbatch) mppi_batch_destroy(ctx->gbatch);
         DevBuf* bufs[] = {&ctx->poly_verts, &ctx->poly_tab_a, &ctx->poly_tab_b, &ctx->rects,
                           &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
-                          &ctx->path, &ctx->sync_ctr, &ctx->cloud_keys, &ctx->cloud_first, &ctx->cloud_cell,
+                          &ctx->path, &ctx->cloud_keys, &ctx->cloud_first, &ctx->cloud_cell,
                           &ctx->cloud_r2, &ctx->cloud_flag, &ctx->cloud_excl, &ctx->cloud_misc,
                           &ctx->eps_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
                           &ctx->key, &ctx->key64, &ctx->unew, &ctx->nom_poses,
@@ -380,30 +378,22 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
         HIP_TRY(ctx, hipMemcpyAsync(D.J, ctx->jt.p, sizeof(float) * A.K, hipMemcpyDeviceToDevice, ctx->stream));
     // 3. weights and update
     HIP_TRY(ctx, ctx->unew.ensure(sizeof(float) * T * nu));
+    HIP_TRY(ctx, launch_update(A, ctx->jt.as<float>(), ctx->eps_ws.as<float>(), dU,
+                               ctx->unew.as<float>(), D.w, ctx->stream));
+    // 4. validation
     HIP_TRY(ctx, ctx->key_nom.ensure(sizeof(unsigned int) * T));
     if (prm->validate) {
-        // 3-4. update with the nominal re-rollout in its last workgroup, then
-        // the validation distances with validation, shift / reset in theirs
         HIP_TRY(ctx, ctx->nom_poses.ensure(sizeof(float4) * T));
-        HIP_TRY(ctx, launch_update_nominal(A, ctx->jt.as<float>(), ctx->eps_ws.as<float>(), dU,
-                                           ctx->unew.as<float>(), D.w, ctx->nom_poses.as<float4>(),
-                                           ctx->key_nom.as<unsigned int>(), ctx->sync_ctr.as<int>(),
-                                           ctx->stream));
+        HIP_TRY(ctx, launch_nominal(A, ctx->unew.as<float>(), ctx->nom_poses.as<float4>(),
+                                    ctx->key_nom.as<unsigned int>(), ctx->stream));
         PoseTime ptn{1, A.T, A.state_offset, A.dt};
-        DminLaunch L = dmin_launch(ctx, ctx->nom_poses.as<float4>(), A.T, ptn, kind,
-                                   ctx->key_nom.as<unsigned int>(), nullptr);
-        L.block = A.T <= 64 ? 64 : 128;
-        FinalizeArgs F{ctx->nom_poses.as<float4>(), ctx->unew.as<float>(), dU, ctx->out.as<float>(),
-                       D.U_upd, D.d_nom, D.J_nom};
-        HIP_TRY(ctx, launch_validate(L, A, F, ctx->sync_ctr.as<int>() + 1, ctx->stream));
-    } else {
-        // 3-4. update, then execute and shift
-        HIP_TRY(ctx, launch_update(A, ctx->jt.as<float>(), ctx->eps_ws.as<float>(), dU,
-                                   ctx->unew.as<float>(), D.w, ctx->stream));
-        HIP_TRY(ctx, launch_finalize(A, 0, ctx->key_nom.as<unsigned int>(), ctx->nom_poses.as<float4>(),
-                                     ctx->unew.as<float>(), dU, ctx->out.as<float>(), D.U_upd, D.d_nom,
-                                     D.J_nom, ctx->stream));
+        if (int rc = run_dmin(ctx, ctx->nom_poses.as<float4>(), A.T, ptn, kind,
+                              ctx->key_nom.as<unsigned int>(), nullptr))
+            return rc;
     }
+    HIP_TRY(ctx, launch_finalize(A, prm->validate ? 1 : 0, ctx->key_nom.as<unsigned int>(),
+                                 ctx->nom_poses.as<float4>(), ctx->unew.as<float>(), dU,
+                                 ctx->out.as<float>(), D.U_upd, D.d_nom, D.J_nom, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_out, ctx->out.p, OUT_FLOATS * sizeof(float), hipMemcpyDeviceToHost,
                                 ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

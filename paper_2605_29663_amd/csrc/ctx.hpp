@@ -79,7 +79,6 @@ struct mppi_ctx_s {
     DevBuf cloud_keys, cloud_first, cloud_cell, cloud_r2, cloud_flag, cloud_excl, cloud_misc;
     // step workspaces
     DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom, out;
-    DevBuf sync_ctr;  // last-workgroup counters of the fused launches (0 between launches)
     float* h_out = nullptr;  // pinned
     // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
     std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
@@ -275,7 +274,8 @@ inline PointArgs point_args(mppi_ctx ctx) {
 // estimate how many workgroups are resident at once.
 inline int dmin_waves_per_simd(int kind, int padded) {
     if (kind == 1) return 8;
-    return padded <= 8 ? 6 : padded <= 16 ? 4 : padded <= 20 ? 3 : 2;
+    // above 16 vertices a lane pair shares a pose (half the edges per lane)
+    return padded <= 8 ? 6 : padded <= 16 ? 4 : 3;
 }
 
 // Default tile shape: chunks of at least 32 points, and a workgroup count
@@ -283,7 +283,8 @@ inline int dmin_waves_per_simd(int kind, int padded) {
 // last round is not a nearly empty tail (all workgroups do equal work).
 inline void choose_tiles(int kind, int padded, int npose, int n_points, int& block, int& nchunk, int& chunk) {
     block = npose >= 4096 ? 256 : 64;
-    const int pose_blocks = std::max(1, (npose + block - 1) / block);
+    const int lanes = (kind == 0 && padded > 16) ? 2 : 1;  // lanes per pose
+    const int pose_blocks = std::max(1, (lanes * npose + block - 1) / block);
     const int resident = 256 * 4 * dmin_waves_per_simd(kind, padded) / (block / WAVE);
     // a pass over few poses (the validation rollout) is bound by the serial
     // point loop of one wave: split the points finer

@@ -118,26 +118,6 @@ hipError_t launch_finalize(const StepArgs& P, int validate, const unsigned int* 
                            const float4* nom, const float* Unew, float* U, float* out,
                            float* diag_unew, float* diag_dnom, float* diag_jnom, hipStream_t s);
 
-// Fused launches of the single-scene step (one launch boundary fewer each):
-// update + nominal re-rollout (the last of the T update workgroups rolls the
-// nominal out), and validation distances + finalize (the last point chunk of
-// the validation pass validates, shifts or resets and writes the result).
-// `counter` is a device int that is 0 between launches.
-struct FinalizeArgs {
-    const float4* nom;
-    const float* Unew;
-    float* U;
-    float* out;
-    float* diag_unew;
-    float* diag_dnom;
-    float* diag_jnom;
-};
-hipError_t launch_update_nominal(const StepArgs& P, const float* jt, const float* eps_ws,
-                                 const float* U, float* Unew, float* diag_w, float4* nom,
-                                 unsigned int* key_nom, int* counter, hipStream_t s);
-hipError_t launch_validate(const DminLaunch& L, const StepArgs& P, const FinalizeArgs& F,
-                           int* counter, hipStream_t s);
-
 // ---------------------------------------------------------------- batched path
 // Per-step arguments of one scene (refreshed by one host-to-device copy per
 // step, so a captured graph replays with new poses, seeds and nominals).

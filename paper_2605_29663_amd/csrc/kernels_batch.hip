@@ -57,9 +57,9 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
 #define EMPPI_PAIR(P)                                                                         \
     case P:                                                                                   \
         if (moving)                                                                           \
-            dmin_poly_pair_range<P / 2, true>(q, tau, S.pts, c0, c1, S.verts, lds, best);     \
+            dmin_poly_pair_range<P / 2, true>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi); \
         else                                                                                  \
-            dmin_poly_pair_range<P / 2, false>(q, tau, S.pts, c0, c1, S.verts, lds, best);    \
+            dmin_poly_pair_range<P / 2, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);\
         return;
 #define EMPPI_RECT(P)                                                                         \
     case P:                                                                                   \

@@ -3,7 +3,6 @@
 // and the obstacle-point compaction that implements the validity mask.
 // The per-lane work is in sdf_device.hpp (shared with the batched kernel).
 #include "sdf_device.hpp"
-#include "step_device.hpp"
 
 namespace emppi {
 
@@ -43,6 +42,34 @@ void k_dmin_poly(const float4* __restrict__ poses, int npose,
     }
 }
 
+// Polygons of more than 16 padded vertices: a lane pair per pose, each lane
+// holding half the edges (PolyHalf), the even lane merges the pose's key.
+template <int HB, bool MOVING, bool ARGMIN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_dmin_poly_pair(const float4* __restrict__ poses, int npose, PoseTime pt, PointArgs pts,
+                      int chunk, const float2* __restrict__ verts, unsigned int* __restrict__ key,
+                      unsigned long long* __restrict__ key64) {
+    extern __shared__ float lds[];
+    const int g = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 1);
+    const bool live = g < npose;
+    const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
+    const float tau = MOVING ? pose_tau(pt, g) : 0.0f;
+    const int nv = *pts.n_valid;
+    const int c0 = blockIdx.y * chunk;
+    const int c1 = min(c0 + chunk, nv);
+    float best;
+    int besti;
+    dmin_poly_pair_range<HB, MOVING, ARGMIN>(q, tau, pts, c0, c1, verts, lds, best, besti);
+    if (live && (threadIdx.x & 1) == 0) {
+        if (ARGMIN) {
+            const unsigned int idx = besti >= 0 ? static_cast<unsigned int>(pts.idx[besti]) : 0xFFFFFFFFu;
+            atomicMin(&key64[g], (static_cast<unsigned long long>(dkey(best)) << 32) | idx);
+        } else {
+            atomicMin(&key[g], dkey(best));
+        }
+    }
+}
+
 template <int RP, bool MOVING, bool ARGMIN>
 __global__ __launch_bounds__(256) void k_dmin_rect(const float4* __restrict__ poses, int npose,
                                                    PoseTime pt, PointArgs pts, int chunk,
@@ -68,59 +95,6 @@ __global__ __launch_bounds__(256) void k_dmin_rect(const float4* __restrict__ po
             atomicMin(&key[g], dkey(best));
         }
     }
-}
-
-// Validation pass fused with the finalize stage: the T nominal poses in one
-// workgroup row (blockDim >= T), point chunks over grid y; the workgroup that
-// completes the pass validates, shifts or resets and writes the result.
-template <int BP, bool MOVING>
-__global__ __launch_bounds__(128) void k_validate_poly(const float4* __restrict__ poses, int npose,
-                                                       PoseTime pt, PointArgs pts, int chunk,
-                                                       const float2* __restrict__ verts,
-                                                       unsigned int* __restrict__ key,
-                                                       StepArgs P, FinalizeArgs F,
-                                                       int* __restrict__ counter) {
-    extern __shared__ float lds[];
-    __shared__ int flag;
-    const int g = threadIdx.x;
-    const bool live = g < npose;
-    const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
-    const float tau = MOVING ? pose_tau(pt, g) : 0.0f;
-    const int nv = *pts.n_valid;
-    const int c0 = blockIdx.y * chunk;
-    const int c1 = min(c0 + chunk, nv);
-    float best;
-    int besti;
-    dmin_poly_range<BP, MOVING, false>(q, tau, pts, c0, c1, verts, lds, best, besti);
-    if (live) atomicMin(&key[g], dkey(best));
-    if (last_block(counter, gridDim.y, &flag))
-        finalize_block<true>(P, 1, key, F.nom, F.Unew, F.U, F.out, F.diag_unew, F.diag_dnom,
-                             F.diag_jnom, lds);
-}
-
-template <int RP, bool MOVING>
-__global__ __launch_bounds__(128) void k_validate_rect(const float4* __restrict__ poses, int npose,
-                                                       PoseTime pt, PointArgs pts, int chunk,
-                                                       const float4* __restrict__ rects,
-                                                       unsigned int* __restrict__ key,
-                                                       StepArgs P, FinalizeArgs F,
-                                                       int* __restrict__ counter) {
-    extern __shared__ float lds[];
-    __shared__ int flag;
-    const int g = threadIdx.x;
-    const bool live = g < npose;
-    const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
-    const float tau = MOVING ? pose_tau(pt, g) : 0.0f;
-    const int nv = *pts.n_valid;
-    const int c0 = blockIdx.y * chunk;
-    const int c1 = min(c0 + chunk, nv);
-    float best;
-    int besti;
-    dmin_rect_range<RP, MOVING, false>(q, tau, pts, c0, c1, rects, lds, best, besti);
-    if (live) atomicMin(&key[g], dkey(best));
-    if (last_block(counter, gridDim.y, &flag))
-        finalize_block<true>(P, 1, key, F.nom, F.Unew, F.U, F.out, F.diag_unew, F.diag_dnom,
-                             F.diag_jnom, lds);
 }
 
 __global__ void k_key_init(unsigned int* __restrict__ key, unsigned long long* __restrict__ key64,
@@ -257,12 +231,28 @@ hipError_t launch_rect_t(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t
     return hipGetLastError();
 }
 
+template <int HB, bool MOVING, bool ARGMIN>
+hipError_t launch_pair_t(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_dmin_poly_pair<HB, MOVING, ARGMIN>), grid, dim3(L.block), lds, s, L.poses,
+                       L.npose, L.pt, L.pts, L.chunk, L.verts, L.key, L.key64);
+    return hipGetLastError();
+}
+
 template <int P>
 hipError_t launch_poly(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
-    if (L.pts.vx) return L.argmin ? launch_poly_t<P, true, true>(L, grid, lds, s)
-                                  : launch_poly_t<P, true, false>(L, grid, lds, s);
-    return L.argmin ? launch_poly_t<P, false, true>(L, grid, lds, s)
-                    : launch_poly_t<P, false, false>(L, grid, lds, s);
+    if constexpr (P > 16) {
+        // two lanes per pose
+        const dim3 g2((2 * L.npose + L.block - 1) / L.block, grid.y);
+        if (L.pts.vx) return L.argmin ? launch_pair_t<P / 2, true, true>(L, g2, lds, s)
+                                      : launch_pair_t<P / 2, true, false>(L, g2, lds, s);
+        return L.argmin ? launch_pair_t<P / 2, false, true>(L, g2, lds, s)
+                        : launch_pair_t<P / 2, false, false>(L, g2, lds, s);
+    } else {
+        if (L.pts.vx) return L.argmin ? launch_poly_t<P, true, true>(L, grid, lds, s)
+                                      : launch_poly_t<P, true, false>(L, grid, lds, s);
+        return L.argmin ? launch_poly_t<P, false, true>(L, grid, lds, s)
+                        : launch_poly_t<P, false, false>(L, grid, lds, s);
+    }
 }
 
 template <int P>
@@ -310,54 +300,6 @@ hipError_t launch_dmin(const DminLaunch& L, hipStream_t s) {
     case 16: return launch_rect<16>(L, grid, lds, s);
     case 24: return launch_rect<24>(L, grid, lds, s);
     case 32: return launch_rect<32>(L, grid, lds, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int P, bool MOVING>
-hipError_t launch_validate_poly_t(const DminLaunch& L, const StepArgs& A, const FinalizeArgs& F,
-                                  int* counter, dim3 grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_validate_poly<P, MOVING>), grid, dim3(L.block), lds, s, L.poses, L.npose,
-                       L.pt, L.pts, L.chunk, L.verts, L.key, A, F, counter);
-    return hipGetLastError();
-}
-
-template <int P, bool MOVING>
-hipError_t launch_validate_rect_t(const DminLaunch& L, const StepArgs& A, const FinalizeArgs& F,
-                                  int* counter, dim3 grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_validate_rect<P, MOVING>), grid, dim3(L.block), lds, s, L.poses, L.npose,
-                       L.pt, L.pts, L.chunk, L.rects, L.key, A, F, counter);
-    return hipGetLastError();
-}
-
-hipError_t launch_validate(const DminLaunch& L, const StepArgs& A, const FinalizeArgs& F,
-                           int* counter, hipStream_t s) {
-    // one workgroup row holds all T poses (finalize needs one thread per step)
-    if (L.npose > L.block || L.block > 128 || L.argmin) return hipErrorInvalidValue;
-    const dim3 grid(1, L.nchunk);
-    const size_t lds = static_cast<size_t>(DMIN_TILE) * (L.pts.vx ? 16 : 8);
-    const bool mv = L.pts.vx != nullptr;
-    if (L.kind == 0) {
-        switch (L.padded) {
-#define EMPPI_CASE(P)                                                                          \
-    case P:                                                                                    \
-        return mv ? launch_validate_poly_t<P, true>(L, A, F, counter, grid, lds, s)            \
-                  : launch_validate_poly_t<P, false>(L, A, F, counter, grid, lds, s);
-            EMPPI_CASE(4) EMPPI_CASE(6) EMPPI_CASE(8) EMPPI_CASE(10) EMPPI_CASE(12) EMPPI_CASE(14)
-            EMPPI_CASE(16) EMPPI_CASE(18) EMPPI_CASE(20) EMPPI_CASE(22) EMPPI_CASE(24)
-            EMPPI_CASE(26) EMPPI_CASE(28) EMPPI_CASE(30) EMPPI_CASE(32)
-#undef EMPPI_CASE
-        default: return hipErrorInvalidValue;
-        }
-    }
-    switch (L.padded) {
-#define EMPPI_CASE(P)                                                                          \
-    case P:                                                                                    \
-        return mv ? launch_validate_rect_t<P, true>(L, A, F, counter, grid, lds, s)            \
-                  : launch_validate_rect_t<P, false>(L, A, F, counter, grid, lds, s);
-        EMPPI_CASE(1) EMPPI_CASE(2) EMPPI_CASE(3) EMPPI_CASE(4) EMPPI_CASE(6) EMPPI_CASE(8)
-        EMPPI_CASE(12) EMPPI_CASE(16) EMPPI_CASE(24) EMPPI_CASE(32)
-#undef EMPPI_CASE
     default: return hipErrorInvalidValue;
     }
 }

@@ -50,30 +50,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(
     finalize_block(P, validate, key_nom, nom, Unew, U, out, diag_unew, diag_dnom, diag_jnom, sh);
 }
 
-__global__ __launch_bounds__(256) void k_update_nominal(StepArgs P, const float* __restrict__ jt,
-                                                        const float* __restrict__ eps_ws,
-                                                        const float* __restrict__ U,
-                                                        float* __restrict__ Unew,
-                                                        float* __restrict__ diag_w,
-                                                        float4* __restrict__ nom,
-                                                        unsigned int* __restrict__ key_nom,
-                                                        int* __restrict__ counter) {
-    __shared__ float sh[16];
-    __shared__ float lds[NOM_LDS_FLOATS];
-    __shared__ int flag;
-    update_block(P, jt, eps_ws, U, Unew, diag_w, blockIdx.x, sh);
-    if (last_block(counter, gridDim.x, &flag)) nominal_block(P, Unew, nom, key_nom, lds);
-}
-
 }  // namespace
-
-hipError_t launch_update_nominal(const StepArgs& P, const float* jt, const float* eps_ws,
-                                 const float* U, float* Unew, float* diag_w, float4* nom,
-                                 unsigned int* key_nom, int* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_nominal, dim3(P.T), dim3(256), 0, s, P, jt, eps_ws, U, Unew, diag_w,
-                       nom, key_nom, counter);
-    return hipGetLastError();
-}
 
 hipError_t launch_rollout(const StepArgs& P, const float* U, const RolloutOut& o, hipStream_t s) {
     hipLaunchKernelGGL(k_rollout, dim3(P.Kpad / WAVE), dim3(ROLL_THREADS), 0, s, P, U, o);

@@ -264,13 +264,14 @@ __device__ __forceinline__ void dmin_poly_range(float4 q, float tau, const Point
 // Same with a lane pair per pose (2 HB padded vertices, see PolyHalf); both
 // lanes of a pair return the pose's minimum.  Every lane of the workgroup
 // must call it with the same range.
-template <int HB, bool MOVING>
+template <int HB, bool MOVING, bool ARGMIN = false>
 __device__ __forceinline__ void dmin_poly_pair_range(float4 q, float tau, const PointArgs& pts,
                                                      int c0, int c1, const float2* __restrict__ verts,
-                                                     float* lds, float& best) {
+                                                     float* lds, float& best, int& besti) {
     PolyHalf<HB> F;
     F.init(verts, (threadIdx.x & 1) * HB, q.z, q.w);
     best = INFINITY;
+    besti = -1;
     for (int t0 = c0; t0 < c1; t0 += DMIN_TILE) {
         const int tn = min(DMIN_TILE, c1 - t0);
         __syncthreads();
@@ -284,14 +285,15 @@ __device__ __forceinline__ void dmin_poly_pair_range(float4 q, float tau, const 
             point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
             F.eval(dx0, dy0, m0, o0);
             F.eval(dx1, dy1, m1, o1);
-            best = fminf(best, fminf(pair_combine(m0, o0), pair_combine(m1, o1)));
+            take<ARGMIN>(pair_combine(m0, o0), t0 + i, best, besti);
+            take<ARGMIN>(pair_combine(m1, o1), t0 + i + 1, best, besti);
         }
         if (i < tn) {
             float dx, dy, m;
             bool o;
             point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
             F.eval(dx, dy, m, o);
-            best = fminf(best, pair_combine(m, o));
+            take<ARGMIN>(pair_combine(m, o), t0 + i, best, besti);
         }
     }
 }

@@ -357,7 +357,6 @@ __device__ __forceinline__ void nominal_block(const StepArgs& P, const float* __
 // if unsafe), is what the hybrid-mode selection compares across modes.
 // out = (u*_0, u*_1, u*_2, valid, J_nom, 0, 0, 0).  One thread per horizon
 // step (FIN_THREADS threads); sh: 16 floats.
-template <bool COHERENT = false>
 __device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
                                                const unsigned int* __restrict__ key_nom,
                                                const float4* __restrict__ nom,
@@ -370,12 +369,7 @@ __device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
     int bad = 0;
     float term = 0.0f;
     if (validate && h < T) {
-        // keys merged by other workgroups of the same launch are read at the
-        // device-coherent level (COHERENT); after a launch boundary plain loads do
-        const unsigned int kv =
-            COHERENT ? __hip_atomic_load(&key_nom[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : key_nom[h];
-        const float sq = dkey_value(kv);
+        const float sq = dkey_value(key_nom[h]);
         const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
         bad = !(d >= P.d_safe);
         if (diag_dnom) diag_dnom[h] = d;
@@ -402,25 +396,6 @@ __device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
         for (int k = 5; k < OUT_FLOATS; ++k) out[k] = 0.0f;
         if (diag_jnom) diag_jnom[0] = jn;
     }
-}
-
-// "Last workgroup" hand-off of a fused launch: every workgroup publishes its
-// writes and counts itself; the one that completes the count (the launch's
-// last) resets the counter for the next launch and returns true, after an
-// acquire fence, so it sees every other workgroup's results.  No workgroup
-// waits, so the hand-off cannot stall.  sh: one int of LDS.
-__device__ __forceinline__ bool last_block(int* counter, int total, int* sh) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int done = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        *sh = done == total - 1;
-        if (*sh) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const bool last = *sh != 0;
-    if (last) __threadfence();
-    return last;
 }
 
 }  // namespace emppi
