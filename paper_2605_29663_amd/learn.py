@@ -165,6 +165,21 @@ def nominal_cost(ctx, prm, q, U):
     return float(D["J"][0].item())
 
 
+def learned_update(net, ctx, prm, q, U_shift, seed, K, step=0):
+    """One MPPI update at K rollouts from the proposal's mean, or from the
+    shifted nominal when the network's output is not finite or the mean's
+    noise-free cost is not lower.  Returns (u*, valid, diagnostics, fallback)."""
+    net.set_scaling(prm)
+    f = net.features(ctx, torch.tensor(np.asarray(q, np.float32)[None], device="cuda"),
+                     U_shift[None].contiguous())
+    finite = bool(torch.isfinite(net.forward(f)).all())
+    mu = net.mean(f)[0].contiguous()
+    fallback = not finite or not (nominal_cost(ctx, prm, q, mu) < nominal_cost(ctx, prm, q, U_shift))
+    U = (U_shift if fallback else mu).clone().contiguous()
+    u, valid, D = ctx.mppi_step(dict(prm, K=K, validate=1), q, U, seed, step, diag=True)
+    return u, valid, D, fallback
+
+
 def evaluate(net, n_states=1000, n_parallel=64, warm_steps=40, seed0=HELDOUT_SEED0,
              K_big=4096, K_small=1024, repeats=4, log=print):
     """Held-out comparison.  For each state, `repeats` independent updates of
@@ -190,19 +205,16 @@ def evaluate(net, n_states=1000, n_parallel=64, warm_steps=40, seed0=HELDOUT_SEE
                     break
                 ctx, p = E.ctxs[s], E.prms[s]
                 q = qb[s]
-                net.set_scaling(p)
-                f = net.features(ctx, torch.tensor(q[None], device="cuda"), Ub[s:s + 1])
-                mu = net.mean(f)[0].contiguous()
-                fb = nominal_cost(ctx, p, q, mu) > nominal_cost(ctx, p, q, Ub[s])
-                if fb:
-                    mu = Ub[s].clone().contiguous()
                 res = np.zeros(3)
+                fb = False
                 for r in range(repeats):
                     seed = int(seed0 + 7919 * len(rows) + 104729 * r)
-                    for j, (K, U0) in enumerate(((K_big, Ub[s]), (K_small, Ub[s]), (K_small, mu))):
-                        U = U0.clone().contiguous()
+                    for j, K in enumerate((K_big, K_small)):
+                        U = Ub[s].clone().contiguous()
                         _, _, D = ctx.mppi_step(dict(p, K=K, validate=1), q, U, seed, 0, diag=True)
                         res[j] += float(D["J_nom"][0].item()) / repeats
+                    _, _, D, fb = learned_update(net, ctx, p, q, Ub[s], seed, K_small)
+                    res[2] += float(D["J_nom"][0].item()) / repeats
                 rows.append(res)
                 fallback.append(bool(fb))
             log(f"evaluate: {len(rows)} states, {time.time() - t0:.0f} s")

@@ -201,3 +201,25 @@ def test_residual_mode_mean_and_targets(pkg):
     net.set_residual(0.0)
     np.testing.assert_allclose(net.mean(f).cpu().numpy(), np.clip(mid + half * y, lo, hi),
                                rtol=1e-6, atol=1e-6)
+
+
+def test_training_resume_is_bitwise(pkg, tmp_path):
+    """Checkpoint / resume: 6 Adam steps, save, load into a new proposal, 6
+    more, equal bit for bit to 12 uninterrupted steps (weights and the Adam
+    state travel in the file; every kernel is deterministic)."""
+    import torch
+    net, theta, Xd, X, Y = _setup(pkg, M=256, seed=11)
+    Yd = torch.tensor(Y, device="cuda")
+    ref = pkg.Proposal(T, NU, hidden=H, max_batch=512)
+    ref.set_params(theta.astype(np.float32))
+    for _ in range(12):
+        ref.train_step(Xd, Yd, lr=1e-3, want_loss=False)
+    for _ in range(6):
+        net.train_step(Xd, Yd, lr=1e-3, want_loss=False)
+    path = tmp_path / "ckpt.bin"
+    net.save(path)
+    res = pkg.Proposal(T, NU, hidden=H, max_batch=512)
+    res.load(path)
+    for _ in range(6):
+        res.train_step(Xd, Yd, lr=1e-3, want_loss=False)
+    np.testing.assert_array_equal(res.get_params(), ref.get_params())

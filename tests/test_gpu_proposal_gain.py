@@ -41,3 +41,25 @@ def test_trained_proposal_beats_plain_at_equal_rollouts(pkg):
     assert g["states_lower"] > g["states_higher"], s
     # and the final cost stays within 2 % of plain MPPI with 4x the rollouts
     assert s["learned_small_over_plain_big"]["ratio"] < 1.02 + 0.05, s
+
+
+def test_broken_network_falls_back_to_plain(pkg):
+    """NaN weights: the mean maps to the box edge, loses the noise-free cost
+    comparison, and the update is the plain one from the shifted nominal, bit
+    for bit."""
+    import torch
+    from paper_2605_29663_amd import learn, scenes
+    sc = learn.corridor_scene(learn.HELDOUT_SEED0 + 42)
+    prm = learn.scene_params(sc, 512)
+    ctx = learn.make_context(sc)
+    net = pkg.Proposal(40, 2, hidden=256, max_batch=8)
+    net.set_params(np.full(net.n_params, np.nan, dtype=np.float32))
+    q = np.float32([0.1, 0.0, 0.05])
+    U_shift = torch.zeros((40, 2), device="cuda")
+    u, v, D, fb = learn.learned_update(net, ctx, prm, q, U_shift, seed=3, K=512)
+    assert fb
+    U = U_shift.clone()
+    u2, v2, D2 = ctx.mppi_step(dict(prm, K=512, validate=1), q, U, 3, 0, diag=True)
+    np.testing.assert_array_equal(u, u2)
+    assert v == v2
+    assert torch.equal(D["U_upd"], D2["U_upd"])
