@@ -133,6 +133,17 @@ int plan(mppi_batch b, double work_per_item) {
     std::vector<size_t> off(n * 9);
     size_t total = 0;
     std::vector<int> nchunk(n), chunk(n), nchunk_nom(n), chunk_nom(n);
+    // small batches: shrink the items so that the sampled-rollout pass still
+    // has about two rounds of resident workgroups (work_per_item is a target
+    // for large batches, where LPT balance needs few, big items)
+    double total_pairs = 0.0;
+    for (int s = 0; s < n; ++s) {
+        const mppi_params& P = b->prms[s];
+        mppi_ctx c = b->scenes[s];
+        const int padded = P.footprint_kind == 0 ? c->BP : c->RP;
+        total_pairs += static_cast<double>(b->args[s].Kpad) * P.T * std::max(c->n_points, 0) * padded;
+    }
+    work_per_item = std::max(65536.0, std::min(work_per_item, total_pairs / 2048.0));
     for (int s = 0; s < n; ++s) {
         const mppi_params& P = b->prms[s];
         mppi_ctx c = b->scenes[s];
