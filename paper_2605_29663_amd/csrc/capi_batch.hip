@@ -22,6 +22,7 @@ struct mppi_batch_s {
     std::vector<const void*> snap_ptr;
     // plan
     double work_per_item = 0.0;     // target point-primitive pairs per queue item
+    int resident[2][DMIN_CLASSES] = {};  // resident workgroups of each persistent launch
     std::vector<SceneBufs> bufs;
     std::vector<SceneDmin> sdm;     // [pass][scene]
     std::vector<DminItem> items[2][DMIN_CLASSES];  // [pass][register class]
@@ -124,6 +125,15 @@ int plan(mppi_batch b, double work_per_item) {
         for (auto& v : p) v.clear();
     b->blk_roll.clear();
     b->blk_upd.clear();
+    int cus = 0;
+    BHIP(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    for (int pass = 0; pass < 2; ++pass)
+        for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
+            const int per_cu = dmin_persistent_blocks_per_cu(cls, pass == 0 ? 256 : 128);
+            if (per_cu <= 0 || cus <= 0)
+                return bfail(b, MPPI_E_HIP, "occupancy query failed for the persistent kernel");
+            b->resident[pass][cls] = cus * per_cu;
+        }
     struct Cost {
         double c;
         DminItem it;
@@ -143,7 +153,8 @@ int plan(mppi_batch b, double work_per_item) {
         const int padded = P.footprint_kind == 0 ? c->BP : c->RP;
         total_pairs += static_cast<double>(b->args[s].Kpad) * P.T * std::max(c->n_points, 0) * padded;
     }
-    work_per_item = std::max(65536.0, std::min(work_per_item, total_pairs / 2048.0));
+    const int slots = *std::max_element(b->resident[0], b->resident[0] + DMIN_CLASSES);
+    work_per_item = std::max(65536.0, std::min(work_per_item, total_pairs / (2.0 * slots)));
     for (int s = 0; s < n; ++s) {
         const mppi_params& P = b->prms[s];
         mppi_ctx c = b->scenes[s];
@@ -251,18 +262,19 @@ int plan(mppi_batch b, double work_per_item) {
     return MPPI_OK;
 }
 
-int persistent_grid(int pass, int cls, size_t n_items) {
-    const int waves = dmin_persistent_waves(cls);
-    const int per_wg_waves = pass == 0 ? 4 : 2;  // 256- or 128-lane tiles
-    const int resident = 256 * 4 * waves / per_wg_waves;
-    return static_cast<int>(std::min<size_t>(n_items, static_cast<size_t>(resident)));
+int persistent_block(int pass) { return pass == 0 ? 256 : 128; }  // lanes per pose tile
+
+// One workgroup per resident slot of the chip (every slot pulls items until
+// the queue is empty), never more than there are items.
+int persistent_grid(mppi_batch b, int pass, int cls, size_t n_items) {
+    return static_cast<int>(std::min<size_t>(n_items, static_cast<size_t>(b->resident[pass][cls])));
 }
 
 int launch_dmin_pass(mppi_batch b, int pass) {
     for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
         const auto& v = b->items[pass][cls];
         if (v.empty()) continue;
-        BHIP(b, launch_dmin_persistent(cls, pass == 0 ? 256 : 128, persistent_grid(pass, cls, v.size()),
+        BHIP(b, launch_dmin_persistent(cls, persistent_block(pass), persistent_grid(b, pass, cls, v.size()),
                                        b->d_sdm.as<SceneDmin>(), b->d_items[pass][cls].as<DminItem>(),
                                        static_cast<int>(v.size()), b->d_counters.as<int>() + DMIN_CLASSES * pass + cls,
                                        b->stream));

@@ -158,10 +158,18 @@ struct DminItem {
     int sd, g0, c, pad;
 };
 
-// Register class of a footprint bucket in the persistent kernel:
-// 0 polygons up to 16 padded vertices, 1 larger polygons, 2 rectangle covers.
-constexpr int DMIN_CLASSES = 3;
-inline int dmin_class(int kind, int padded) { return kind == 1 ? 2 : (padded > 16 ? 1 : 0); }
+// Register class of a footprint bucket in the persistent kernel, each
+// compiled for the occupancy its largest bucket allows without spilling in
+// the point loop: 0 polygons up to 8 padded vertices (6 waves per SIMD),
+// 1 polygons of 10..16 (4 waves), 2 polygons of 18..28 with a lane pair per
+// pose (4 waves), 3 polygons of 30..32 with a lane pair per pose (3 waves),
+// 4 rectangle covers up to 12 boxes (8 waves), 5 larger covers (2 waves).
+constexpr int DMIN_CLASSES = 6;
+inline int dmin_class(int kind, int padded) {
+    if (kind == 1) return padded <= 12 ? 4 : 5;
+    return padded <= 8 ? 0 : padded <= 16 ? 1 : padded <= 28 ? 2 : 3;
+}
+constexpr bool dmin_class_pair(int cls) { return cls == 2 || cls == 3; }
 
 hipError_t launch_batch_reset(int* counters, int n, hipStream_t s);
 hipError_t launch_rollout_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,
@@ -176,7 +184,10 @@ hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs,
                                   hipStream_t s);
 hipError_t launch_finalize_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
                                    hipStream_t s);
-int dmin_persistent_waves(int cls);
+// Workgroups of k_dmin_persistent<cls> (block threads) resident per compute
+// unit on the current device, from the occupancy calculator (registers and
+// the LDS tile); 0 on error.
+int dmin_persistent_blocks_per_cu(int cls, int block);
 int dmin_persistent_lanes_per_pose(int cls);
 
 // ---------------------------------------------------------------- hybrid modes

@@ -38,11 +38,7 @@ __global__ __launch_bounds__(ROLL_THREADS) void k_rollout_b(const SceneStep* __r
     rollout_block(S.P, S.U, o, b.y, lds);
 }
 
-// Footprint bucket dispatch.  Class 0: polygons up to 16 padded vertices
-// (register budget for 3 waves per SIMD); class 1: polygons of 18..32
-// padded vertices, a lane pair per pose, each lane holding half the edges
-// (3 waves); class 2: rectangle covers (2 waves: up to 32
-// boxes are kept in registers).
+// Footprint bucket dispatch over the register classes of dmin_class.
 template <int CLS>
 __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, float4 q, float tau,
                                               int c0, int c1, float* lds, float& best) {
@@ -73,6 +69,10 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
             EMPPI_POLY(4)
             EMPPI_POLY(6)
             EMPPI_POLY(8)
+        default: break;
+        }
+    } else if (CLS == 1) {
+        switch (S.padded) {
             EMPPI_POLY(10)
             EMPPI_POLY(12)
             EMPPI_POLY(14)
@@ -80,22 +80,6 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
         default: break;
         }
     } else if (CLS == 2) {
-        {
-            switch (S.padded) {
-                EMPPI_RECT(1)
-                EMPPI_RECT(2)
-                EMPPI_RECT(3)
-                EMPPI_RECT(4)
-                EMPPI_RECT(6)
-                EMPPI_RECT(8)
-                EMPPI_RECT(12)
-                EMPPI_RECT(16)
-                EMPPI_RECT(24)
-                EMPPI_RECT(32)
-            default: break;
-            }
-        }
-    } else {
         switch (S.padded) {
             EMPPI_PAIR(18)
             EMPPI_PAIR(20)
@@ -103,8 +87,30 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
             EMPPI_PAIR(24)
             EMPPI_PAIR(26)
             EMPPI_PAIR(28)
+        default: break;
+        }
+    } else if (CLS == 3) {
+        switch (S.padded) {
             EMPPI_PAIR(30)
             EMPPI_PAIR(32)
+        default: break;
+        }
+    } else if (CLS == 4) {
+        switch (S.padded) {
+            EMPPI_RECT(1)
+            EMPPI_RECT(2)
+            EMPPI_RECT(3)
+            EMPPI_RECT(4)
+            EMPPI_RECT(6)
+            EMPPI_RECT(8)
+            EMPPI_RECT(12)
+        default: break;
+        }
+    } else {
+        switch (S.padded) {
+            EMPPI_RECT(16)
+            EMPPI_RECT(24)
+            EMPPI_RECT(32)
         default: break;
         }
     }
@@ -115,8 +121,14 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
 }
 
 template <int CLS>
+constexpr int persistent_waves() {
+    constexpr int waves[DMIN_CLASSES] = {6, 4, 4, 3, 8, 2};
+    return waves[CLS];
+}
+
+template <int CLS>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(CLS == 2 ? 2 : 3)))
+__attribute__((amdgpu_waves_per_eu(persistent_waves<CLS>())))
 void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __restrict__ items,
                        int n_items, int* __restrict__ counter) {
     extern __shared__ float lds[];
@@ -125,23 +137,25 @@ void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __rest
         __syncthreads();  // the previous item's LDS tile and `next` are no longer read
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = next;
+        // the item is the same for the whole workgroup: keep it (and all
+        // that is read through it) in scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(next);
         if (it >= n_items) break;
-        const DminItem w = items[it];
-        const SceneDmin& S = sds[w.sd];
-        // class 1: two lanes per pose
-        const int g = w.g0 + static_cast<int>(CLS == 1 ? threadIdx.x >> 1 : threadIdx.x);
+        const DminItem w = wave_uniform(items[it]);
+        const SceneDmin S = wave_uniform(sds[w.sd]);
+        // lane-pair class: two lanes per pose
+        const int g = w.g0 + static_cast<int>(dmin_class_pair(CLS) ? threadIdx.x >> 1 : threadIdx.x);
         const int npose = S.npose;
         const bool live = g < npose;
         const float4 q = live ? S.poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
         const bool moving = S.pts.vx != nullptr;
         const float tau = moving ? pose_tau(S.pt, g) : 0.0f;
-        const int nv = *S.pts.n_valid;
+        const int nv = __builtin_amdgcn_readfirstlane(*S.pts.n_valid);
         const int c0 = w.c * S.chunk;
         const int c1 = min(c0 + S.chunk, nv);
         float best;
         dmin_dispatch<CLS>(S, moving, q, tau, c0, c1, lds, best);
-        if (live && (CLS != 1 || (threadIdx.x & 1) == 0)) atomicMin(&S.key[g], dkey(best));
+        if (live && (!dmin_class_pair(CLS) || (threadIdx.x & 1) == 0)) atomicMin(&S.key[g], dkey(best));
     }
 }
 
@@ -242,8 +256,22 @@ hipError_t launch_hybrid_select(const float* out, const HybridArgs& a, float* re
     return hipGetLastError();
 }
 
-int dmin_persistent_waves(int cls) { return cls == 2 ? 2 : 3; }
-int dmin_persistent_lanes_per_pose(int cls) { return cls == 1 ? 2 : 1; }
+// LDS tile of the persistent kernels, sized for moving points (16 bytes per point)
+constexpr size_t PERSISTENT_LDS = static_cast<size_t>(DMIN_TILE) * 16;
+
+using PersistentKernel = void (*)(const SceneDmin*, const DminItem*, int, int*);
+constexpr PersistentKernel PERSISTENT[DMIN_CLASSES] = {
+    k_dmin_persistent<0>, k_dmin_persistent<1>, k_dmin_persistent<2>, k_dmin_persistent<3>,
+    k_dmin_persistent<4>, k_dmin_persistent<5>};
+
+int dmin_persistent_blocks_per_cu(int cls, int block) {
+    if (cls < 0 || cls >= DMIN_CLASSES) return 0;
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, reinterpret_cast<const void*>(PERSISTENT[cls]), block, PERSISTENT_LDS);
+    return e == hipSuccess ? nb : 0;
+}
+int dmin_persistent_lanes_per_pose(int cls) { return dmin_class_pair(cls) ? 2 : 1; }
 
 hipError_t launch_batch_reset(int* counters, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counters, n);
@@ -260,17 +288,9 @@ hipError_t launch_rollout_batched(const SceneStep* steps, const SceneBufs* bufs,
 hipError_t launch_dmin_persistent(int cls, int block, int grid, const SceneDmin* sds,
                                   const DminItem* items, int n_items, int* counter, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    // LDS tile sized for moving points (16 bytes per point)
-    const size_t lds = static_cast<size_t>(DMIN_TILE) * 16;
-    if (cls == 0)
-        hipLaunchKernelGGL(k_dmin_persistent<0>, dim3(grid), dim3(block), lds, s, sds, items,
-                           n_items, counter);
-    else if (cls == 1)
-        hipLaunchKernelGGL(k_dmin_persistent<1>, dim3(grid), dim3(block), lds, s, sds, items,
-                           n_items, counter);
-    else
-        hipLaunchKernelGGL(k_dmin_persistent<2>, dim3(grid), dim3(block), lds, s, sds, items,
-                           n_items, counter);
+    if (cls < 0 || cls >= DMIN_CLASSES) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(PERSISTENT[cls], dim3(grid), dim3(block), PERSISTENT_LDS, s, sds, items,
+                       n_items, counter);
     return hipGetLastError();
 }
 

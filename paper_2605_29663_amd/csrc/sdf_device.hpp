@@ -65,6 +65,22 @@ __device__ __forceinline__ float signed_sqrt(float s) {
     return s < 0.0f ? -__builtin_sqrtf(-s) : __builtin_sqrtf(s);
 }
 
+// A value that is the same in every lane, moved to scalar registers: every
+// 32-bit word is taken from the first active lane.  For loads the compiler
+// cannot prove uniform and unclobbered (a persistent kernel's descriptors,
+// read after atomics of the previous work item), which would otherwise hold
+// uniform data in vector registers.
+template <typename T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    T r;
+    const int* src = reinterpret_cast<const int*>(&v);
+    int* dst = reinterpret_cast<int*>(&r);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return r;
+}
+
 // Stage points [t0, t0 + tn) of the compacted set into LDS: (x, y) pairs for
 // static sets, (x, y, vx, vy) for moving ones.
 template <bool MOVING>
@@ -242,7 +258,9 @@ __device__ __forceinline__ void dmin_poly_range(float4 q, float tau, const Point
         stage_points<MOVING>(lds, pts, t0, tn);
         __syncthreads();
         int i = 0;
-        if (BP <= 20) {  // two points per iteration while registers allow
+        // two points per iteration while registers allow (a moving point
+        // holds two more registers until its position at tau is formed)
+        if (BP <= (MOVING ? 14 : 20)) {
             for (; i + 2 <= tn; i += 2) {
                 float dx0, dy0, dx1, dy1;
                 point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
@@ -306,7 +324,7 @@ __device__ __forceinline__ void dmin_rect_range(float4 q, float tau, const Point
                                                 float* lds, float& best, int& besti) {
     float4 bx[RP];
 #pragma unroll
-    for (int j = 0; j < RP; ++j) bx[j] = rects[j];
+    for (int j = 0; j < RP; ++j) bx[j] = RP <= 12 ? wave_uniform(rects[j]) : rects[j];
     best = INFINITY;
     besti = -1;
     auto eval = [&](float dx, float dy) {

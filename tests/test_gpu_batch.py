@@ -20,9 +20,10 @@ def pkg():
 
 
 def _mixed_scenes():
-    """Seven small scenes covering every register class (large polygons with
-    static and with moving points), all motion models and a scene without
-    validation."""
+    """Nine small scenes covering every register class of the persistent
+    kernel (small, medium and lane-pair polygons with static and with moving
+    points, small and large rectangle covers), all motion models and a scene
+    without validation."""
     out = []
     p1, s1 = scenes.config("c1", K=192, T=12)
     out.append((p1, s1))
@@ -49,6 +50,15 @@ def _mixed_scenes():
     p7 = scenes.params("c3", K=96, T=7, footprint_kind=0, goal=(2.0, -1.0))
     s7 = {k: (v[:1800] if isinstance(v, np.ndarray) and v.ndim == 1 else v) for k, v in s3.items()}
     out.append((p7, dict(s7, polygon=V19, rects=None)))
+    V31 = scenes.star_polygon(rng, 31)                   # lane pairs, 32 padded vertices
+    p8 = scenes.params("c3", K=80, T=6, footprint_kind=0, goal=(1.0, 2.0))
+    s8 = {k: (v[:900] if isinstance(v, np.ndarray) and v.ndim == 1 else v) for k, v in s3.items()}
+    out.append((p8, dict(s8, polygon=V31, rects=None)))
+    g = np.arange(4) * 0.5 - 0.75                         # 16-box cover on a 4 x 4 grid
+    R16 = np.array([(x, y, 0.2 + 0.05 * rng.uniform(), 0.2 + 0.05 * rng.uniform())
+                    for x in g for y in g], dtype=np.float64)
+    p9 = scenes.params("c3", K=72, T=5, goal=(-1.0, 1.5))
+    out.append((p9, dict(ox=pts[:1200, 0].copy(), oy=pts[:1200, 1].copy(), polygon=None, rects=R16)))
     return out
 
 
