@@ -208,37 +208,44 @@ struct PolyHalf {
         Yend = Yn;
     }
 
-    // Minimum squared distance over this lane's edges and the parity of
-    // their crossings of the ray from (dx, dy).
-    __device__ __forceinline__ void eval(float dx, float dy, float& m, bool& odd) const {
+    // Minimum squared distance over this lane's edges, and the crossing
+    // parities of the ray from (dx, dy) over each lane's edges as a lane mask
+    // of the wave (bit l set: lane l saw an odd number of crossings).  The
+    // parity runs on the scalar unit on the compare masks; every lane of the
+    // wave must be active.
+    __device__ __forceinline__ void eval(float dx, float dy, float& m, unsigned long long& odd) const {
         EdgeEval e = edge_eval(dx, dy, X[0], Y[0], EX[0], EY[0], SX[0], SY[0], SL[0]);
         m = e.d2;
-        bool above = e.above, right = e.right;
-        odd = false;
+        unsigned long long above = __builtin_amdgcn_ballot_w64(e.above);
+        unsigned long long right = __builtin_amdgcn_ballot_w64(e.right);
+        odd = 0;
 #pragma unroll
         for (int b = 1; b < HB; ++b) {
             e = edge_eval(dx, dy, X[b], Y[b], EX[b], EY[b], SX[b], SY[b], SL[b]);
             m = fminf(m, e.d2);
-            odd ^= (above != e.above) & right;
-            above = e.above;
-            right = e.right;
+            const unsigned long long ab = __builtin_amdgcn_ballot_w64(e.above);
+            odd ^= (above ^ ab) & right;
+            above = ab;
+            right = __builtin_amdgcn_ballot_w64(e.right);
         }
-        odd ^= (above != ((dy - Yend) < 0.0f)) & right;
+        odd ^= (above ^ __builtin_amdgcn_ballot_w64((dy - Yend) < 0.0f)) & right;
     }
 };
 
-// Value of the other lane of the pair (lanes 2k, 2k + 1): DPP quad
-// permutation [1, 0, 3, 2].
-__device__ __forceinline__ float pair_swap(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-
-// Signed squared distance from a lane pair's partial results: the smaller
-// minimum, negative when exactly one half saw an odd number of crossings.
-__device__ __forceinline__ float pair_combine(float m, bool odd) {
-    const float sg = odd ? -1.0f : 1.0f;
-    const float mm = fminf(m, pair_swap(m));
-    return (sg * pair_swap(sg)) * mm;
+// Signed squared distance from a lane pair's partial results (lanes 2k,
+// 2k + 1): the smaller minimum, negative when exactly one half saw an odd
+// number of crossings.  The parities combine on the scalar unit (the wave's
+// parity mask XOR the same mask with the bits of each pair swapped); the
+// minima are non-negative, so their integer order is their float order and
+// the partner's value arrives through a DPP quad permutation [1, 0, 3, 2]
+// folded into the integer min.  Every lane of the wave must be active.
+__device__ __forceinline__ float pair_combine(float m, unsigned long long odd) {
+    const unsigned long long partner =
+        ((odd >> 1) & 0x5555555555555555ull) | ((odd << 1) & 0xAAAAAAAAAAAAAAAAull);
+    const bool neg = __builtin_amdgcn_inverse_ballot_w64(odd ^ partner);
+    const int mi = __float_as_int(m);
+    const float mm = __int_as_float(min(mi, __builtin_amdgcn_mov_dpp(mi, 0xB1, 0xF, 0xF, true)));
+    return neg ? -mm : mm;
 }
 
 // Min over the valid points [c0, c1) of the signed squared distance to the
@@ -298,7 +305,7 @@ __device__ __forceinline__ void dmin_poly_pair_range(float4 q, float tau, const 
         int i = 0;
         for (; i + 2 <= tn; i += 2) {
             float dx0, dy0, dx1, dy1, m0, m1;
-            bool o0, o1;
+            unsigned long long o0, o1;
             point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
             point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
             F.eval(dx0, dy0, m0, o0);
@@ -308,7 +315,7 @@ __device__ __forceinline__ void dmin_poly_pair_range(float4 q, float tau, const 
         }
         if (i < tn) {
             float dx, dy, m;
-            bool o;
+            unsigned long long o;
             point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
             F.eval(dx, dy, m, o);
             take<ARGMIN>(pair_combine(m, o), t0 + i, best, besti);
