@@ -66,7 +66,7 @@ def parse():
 def padded_count(kind, count):
     """Primitive count the fused kernel is instantiated for (padding is exact)."""
     if kind == 0:
-        return max(4, (count + 1) // 2 * 2)
+        return max(3, count) if count <= 16 else (count + 1) // 2 * 2
     return next(b for b in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32) if count <= b)
 
 

@@ -158,12 +158,13 @@ struct DminItem {
     int sd, g0, c, pad;
 };
 
-// Register class of a footprint bucket in the persistent kernel, each
-// compiled for the occupancy its largest bucket allows without spilling in
-// the point loop: 0 polygons up to 8 padded vertices (6 waves per SIMD),
-// 1 polygons of 10..16 (4 waves), 2 polygons of 18..28 with a lane pair per
-// pose (4 waves), 3 polygons of 30..32 with a lane pair per pose (3 waves),
-// 4 rectangle covers up to 12 boxes (8 waves), 5 larger covers (2 waves).
+// Register class of a footprint bucket (padded primitive count) in the
+// persistent kernel, each compiled for the occupancy its largest bucket
+// allows without spilling in the point loop: 0 polygons of 3..8 vertices
+// (6 waves per SIMD), 1 polygons of 9..16 (4 waves), 2 polygons padded to
+// 18..28 with a lane pair per pose (4 waves), 3 polygons padded to 30..32
+// with a lane pair per pose (3 waves), 4 rectangle covers up to 12 boxes
+// (8 waves), 5 larger covers (2 waves).
 constexpr int DMIN_CLASSES = 6;
 inline int dmin_class(int kind, int padded) {
     if (kind == 1) return padded <= 12 ? 4 : 5;

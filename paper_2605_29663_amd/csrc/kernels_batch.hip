@@ -66,16 +66,23 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
         return;
     if (CLS == 0) {
         switch (S.padded) {
+            EMPPI_POLY(3)
             EMPPI_POLY(4)
+            EMPPI_POLY(5)
             EMPPI_POLY(6)
+            EMPPI_POLY(7)
             EMPPI_POLY(8)
         default: break;
         }
     } else if (CLS == 1) {
         switch (S.padded) {
+            EMPPI_POLY(9)
             EMPPI_POLY(10)
+            EMPPI_POLY(11)
             EMPPI_POLY(12)
+            EMPPI_POLY(13)
             EMPPI_POLY(14)
+            EMPPI_POLY(15)
             EMPPI_POLY(16)
         default: break;
         }

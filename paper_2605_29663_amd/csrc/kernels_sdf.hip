@@ -266,9 +266,11 @@ hipError_t launch_rect(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s
 }  // namespace
 
 int dmin_padded_count(int kind, int count) {
-    // polygons: even vertex counts (padding repeats vertex 0: zero-length
-    // edges that change neither the minimum nor the crossing parity)
-    if (kind == 0) return count <= 4 ? 4 : ((count + 1) / 2) * 2;
+    // polygons: the exact count up to 16 vertices (one lane per pose), even
+    // counts above (a lane pair per pose, half the edges each); padding
+    // repeats vertex 0: zero-length edges that change neither the minimum
+    // nor the crossing parity
+    if (kind == 0) return count <= 16 ? (count < 3 ? 3 : count) : ((count + 1) / 2) * 2;
     static const int rb[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int b : rb)
         if (count <= b) return b;
@@ -282,9 +284,11 @@ hipError_t launch_dmin(const DminLaunch& L, hipStream_t s) {
         switch (L.padded) {
 #define EMPPI_CASE(P) \
     case P: return launch_poly<P>(L, grid, lds, s);
-            EMPPI_CASE(4) EMPPI_CASE(6) EMPPI_CASE(8) EMPPI_CASE(10) EMPPI_CASE(12) EMPPI_CASE(14)
-            EMPPI_CASE(16) EMPPI_CASE(18) EMPPI_CASE(20) EMPPI_CASE(22) EMPPI_CASE(24)
-            EMPPI_CASE(26) EMPPI_CASE(28) EMPPI_CASE(30) EMPPI_CASE(32)
+            EMPPI_CASE(3) EMPPI_CASE(4) EMPPI_CASE(5) EMPPI_CASE(6) EMPPI_CASE(7) EMPPI_CASE(8)
+            EMPPI_CASE(9) EMPPI_CASE(10) EMPPI_CASE(11) EMPPI_CASE(12) EMPPI_CASE(13)
+            EMPPI_CASE(14) EMPPI_CASE(15) EMPPI_CASE(16) EMPPI_CASE(18) EMPPI_CASE(20)
+            EMPPI_CASE(22) EMPPI_CASE(24) EMPPI_CASE(26) EMPPI_CASE(28) EMPPI_CASE(30)
+            EMPPI_CASE(32)
 #undef EMPPI_CASE
         default: return hipErrorInvalidValue;
         }

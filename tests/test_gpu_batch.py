@@ -20,10 +20,10 @@ def pkg():
 
 
 def _mixed_scenes():
-    """Nine small scenes covering every register class of the persistent
-    kernel (small, medium and lane-pair polygons with static and with moving
-    points, small and large rectangle covers), all motion models and a scene
-    without validation."""
+    """Eleven small scenes covering every register class of the persistent
+    kernel (small, medium and lane-pair polygons, odd and even vertex counts,
+    static and moving points, small and large rectangle covers), all motion
+    models and a scene without validation."""
     out = []
     p1, s1 = scenes.config("c1", K=192, T=12)
     out.append((p1, s1))
@@ -59,6 +59,12 @@ def _mixed_scenes():
                     for x in g for y in g], dtype=np.float64)
     p9 = scenes.params("c3", K=72, T=5, goal=(-1.0, 1.5))
     out.append((p9, dict(ox=pts[:1200, 0].copy(), oy=pts[:1200, 1].copy(), polygon=None, rects=R16)))
+    p10 = scenes.params("c1", K=70, T=6, goal=(-2.0, 0.5))   # odd vertex counts, unpadded
+    out.append((p10, dict(ox=pts[:700, 0].copy(), oy=pts[:700, 1].copy(),
+                          polygon=scenes.star_polygon(rng, 7), rects=None)))
+    p11 = scenes.params("c3", K=66, T=5, footprint_kind=0, goal=(0.5, -2.0))
+    s11 = {k: (v[:600] if isinstance(v, np.ndarray) and v.ndim == 1 else v) for k, v in s3.items()}
+    out.append((p11, dict(s11, polygon=scenes.star_polygon(rng, 13), rects=None)))
     return out
 
 

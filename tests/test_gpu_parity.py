@@ -116,12 +116,23 @@ def _random_poses(rng, K, T, spread=2.0):
     return P.astype(np.float32)
 
 
-@pytest.mark.parametrize("kind,moving,masked,big", [(0, False, False, False), (0, True, True, False),
-                                                    (0, True, True, True), (0, False, False, True),
-                                                    (1, False, True, False), (1, True, False, False)])
-def test_sdf_min_poses(ctx, pkg, orc, kind, moving, masked, big):
-    """big: a 27-vertex polygon (padded to 28: a lane pair per pose)."""
-    rng = np.random.default_rng(10 * kind + 2 * moving + masked + 100 * big)
+FUSED_POLYS = {"towed16": scenes.FOOTPRINT_TOWED16,
+               "star7": scenes.star_polygon(np.random.default_rng(7), 7),
+               "star13": scenes.star_polygon(np.random.default_rng(13), 13),
+               "star27": scenes.star_polygon(np.random.default_rng(27), 27)}
+
+
+@pytest.mark.parametrize("kind,moving,masked,poly", [(0, False, False, "towed16"),
+                                                     (0, True, True, "towed16"),
+                                                     (0, True, True, "star27"),
+                                                     (0, False, False, "star27"),
+                                                     (0, False, True, "star7"),
+                                                     (0, True, False, "star13"),
+                                                     (1, False, True, None), (1, True, False, None)])
+def test_sdf_min_poses(ctx, pkg, orc, kind, moving, masked, poly):
+    """Polygons of odd vertex counts run unpadded (one lane per pose); the
+    27-vertex polygon is padded to 28 (a lane pair per pose)."""
+    rng = np.random.default_rng(10 * kind + 2 * moving + masked + 100 * len(poly or ""))
     K, T, N, dt = 100, 7, 2500, 0.1            # 700 poses (ragged vs 64), 3 LDS tiles
     poses = _random_poses(rng, K, T)
     ox, oy = rng.uniform(-4, 4, N).astype(np.float32), rng.uniform(-4, 4, N).astype(np.float32)
@@ -129,9 +140,7 @@ def test_sdf_min_poses(ctx, pkg, orc, kind, moving, masked, big):
     if moving:
         vx, vy = rng.uniform(-1, 1, N).astype(np.float32), rng.uniform(-1, 1, N).astype(np.float32)
     valid = (rng.uniform(size=N) < 0.6).astype(np.uint8) if masked else None
-    geom = scenes.FOOTPRINT_TOWED16 if kind == 0 else scenes.RECTS_4
-    if big:
-        geom = scenes.star_polygon(np.random.default_rng(27), 27)
+    geom = FUSED_POLYS[poly] if kind == 0 else scenes.RECTS_4
     ctx.set_footprint(kind, geom)
     ctx.set_points(ox, oy, vx, vy, valid)
     d, am = ctx.sdf_min_poses(poses, dt=dt, state_offset=1, kind=kind, argmin=True)
