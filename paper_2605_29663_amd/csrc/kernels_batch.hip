@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(persistent_waves<CLS>())))
 void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __restrict__ items,
                        int n_items, int* __restrict__ counter) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];  // point tiles: 8- and 16-byte LDS accesses
     __shared__ int next;
     for (;;) {
         __syncthreads();  // the previous item's LDS tile and `next` are no longer read

@@ -21,7 +21,7 @@ void k_dmin_poly(const float4* __restrict__ poses, int npose,
                                                    const float2* __restrict__ verts,
                                                    unsigned int* __restrict__ key,
                                                    unsigned long long* __restrict__ key64) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];  // point tiles: 8- and 16-byte LDS accesses
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = g < npose;
     const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 void k_dmin_poly_pair(const float4* __restrict__ poses, int npose, PoseTime pt, PointArgs pts,
                       int chunk, const float2* __restrict__ verts, unsigned int* __restrict__ key,
                       unsigned long long* __restrict__ key64) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];  // point tiles: 8- and 16-byte LDS accesses
     const int g = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 1);
     const bool live = g < npose;
     const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_dmin_rect(const float4* __restrict__ po
                                                    const float4* __restrict__ rects,
                                                    unsigned int* __restrict__ key,
                                                    unsigned long long* __restrict__ key64) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];  // point tiles: 8- and 16-byte LDS accesses
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = g < npose;
     const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
