@@ -94,11 +94,15 @@ typedef struct mppi_params {
 } mppi_params;
 
 /* Graph mode (enable != 0): mppi_step calls without diagnostics (diag NULL)
- * and without profiling replay a captured hipGraph of the whole step (a
- * one-scene batch of this context, see mppi_batch_create: bit-identical
- * results, fewer launch overheads).  The graph is rebuilt when the
- * parameters change and re-planned when points or footprint change.  The
- * call first waits for the context's stream.  Disabling frees it.          */
+ * replay a captured hipGraph of the whole step (a one-scene batch of this
+ * context, see mppi_batch_create: bit-identical results, fewer launch
+ * overheads, the persistent distance kernel).  The first step of a
+ * parameter set builds the batch and autotunes its item size
+ * (mppi_batch_autotune: about 70 launches of the distance pass); the graph
+ * is rebuilt when the parameters change and re-planned when points or
+ * footprint change.  With profiling on (mppi_set_profiling) the batch runs
+ * eagerly and mppi_get_profile reports its distance pass.  The call first
+ * waits for the context's stream.  Disabling frees it.                     */
 MPPI_API int mppi_set_graph(mppi_ctx ctx, int enable);
 
 /* Weak guidance (Section "Problem Statement": a waypoint sequence from an
@@ -337,15 +341,23 @@ MPPI_API int mppi_batch_refresh(mppi_batch b);
 MPPI_API int mppi_step_batched(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
                                const uint64_t* steps, float* u_out, int* valid_out, int use_graph);
 
-/* Tile autotuner of the batch: times the persistent signed-distance pass for
- * queue items of 2^18 .. 2^26 point-primitive pairs (reps launches each, HIP
- * events) and re-plans with the fastest.  *out_work_per_item (may be NULL)
- * receives it.  Results do not depend on the choice.  Synchronous.         */
+/* Tile autotuner of the batch: after a warm-up, times the persistent
+ * signed-distance pass for queue items of 2^16 .. 2^26 point-primitive pairs
+ * (reps launches each, HIP events, a forward and a backward sweep, the
+ * faster of the two kept) and re-plans with the fastest.
+ * *out_work_per_item (may be NULL) receives it.  Results do not depend on
+ * the choice.  Synchronous.                                                 */
 MPPI_API int mppi_batch_autotune(mppi_batch b, int reps, double* out_work_per_item);
 
+/* Fix the queue item size: work_per_item point-primitive pairs per item
+ * (at least 2^16 are used), or 0 for the default (2^22, shrunk for small
+ * batches to about two rounds of resident workgroups).  Re-plans; results
+ * do not depend on the size.  Errors: MPPI_E_ARG (negative, NaN, > 1e15). */
+MPPI_API int mppi_batch_set_work(mppi_batch b, double work_per_item);
+
 /* Size of the current plan: queue items of the sampled-rollout pass and of
- * the validation pass, and the target pairs per item.  Any pointer may be
- * NULL.                                                                     */
+ * the validation pass, and the pairs per item the plan uses.  Any pointer
+ * may be NULL.                                                              */
 MPPI_API int mppi_batch_info(mppi_batch b, long long* items_main, long long* items_validation,
                              double* work_per_item);
 

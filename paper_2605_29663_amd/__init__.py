@@ -31,7 +31,7 @@ EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footpri
            "mppi_set_profiling", "mppi_get_profile",
            "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
            "mppi_batch_u_offsets", "mppi_batch_refresh", "mppi_step_batched",
-           "mppi_batch_autotune", "mppi_batch_info", "mppi_batch_nominal_costs",
+           "mppi_batch_autotune", "mppi_batch_set_work", "mppi_batch_info", "mppi_batch_nominal_costs",
            "mppi_batch_set_profiling", "mppi_batch_get_profile",
            "mppi_hybrid_create", "mppi_hybrid_destroy", "mppi_hybrid_last_error",
            "mppi_hybrid_batch", "mppi_hybrid_step",
@@ -130,6 +130,7 @@ def load():
     L.mppi_batch_refresh.argtypes = [vp]
     L.mppi_step_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, i]
     L.mppi_batch_autotune.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
+    L.mppi_batch_set_work.argtypes = [vp, ctypes.c_double]
     L.mppi_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
     L.mppi_batch_nominal_costs.argtypes = [vp, vp]
@@ -437,6 +438,10 @@ class Batch:
         w = ctypes.c_double()
         self._check(self.lib.mppi_batch_autotune(self.h, int(reps), ctypes.byref(w)))
         return w.value
+
+    def mppi_batch_set_work(self, work_per_item=0.0):
+        """Queue item size in point-primitive pairs (0: the default); re-plans."""
+        self._check(self.lib.mppi_batch_set_work(self.h, float(work_per_item)))
 
     def mppi_batch_info(self):
         a, b, w = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_double()

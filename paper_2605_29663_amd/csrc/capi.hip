@@ -316,29 +316,44 @@ int mppi_set_graph(mppi_ctx ctx, int enable) {
 namespace {
 
 // Graph-mode step: a one-scene batch of this context (bit-identical to the
-// eager step), rebuilt when the parameters change and re-planned when the
-// points or the footprint changed.
+// eager step) with an autotuned queue item size, rebuilt when the parameters
+// change and re-planned when the points or the footprint changed.  With
+// profiling on, the batch runs eagerly and its distance pass is timed.
 int step_via_graph(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, uint64_t seed,
                    uint64_t step, float* u_out, int* valid_out) {
     if (ctx->gbatch && std::memcmp(&ctx->gprm, prm, sizeof(mppi_params)) != 0) {
         mppi_batch_destroy(ctx->gbatch);
         ctx->gbatch = nullptr;
     }
+    // work the caller queued on the context's stream (nominal, points) comes first
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (!ctx->gbatch) {
         if (int rc = mppi_batch_create(&ctx->gbatch, &ctx, prm, 1, nullptr))
             return fail(ctx, rc, "graph mode: %s", mppi_batch_last_error(nullptr));
         ctx->gprm = *prm;
+        if (int rc = mppi_batch_autotune(ctx->gbatch, 2, nullptr))
+            return fail(ctx, rc, "graph mode: %s", mppi_batch_last_error(ctx->gbatch));
     }
-    // work the caller queued on the context's stream (nominal, points) comes first
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int use_graph = ctx->prof ? 0 : 1;
+    if (ctx->prof && mppi_batch_set_profiling(ctx->gbatch, 1) != MPPI_OK)
+        return fail(ctx, MPPI_E_HIP, "graph mode: %s", mppi_batch_last_error(ctx->gbatch));
     int valid = 0;
     float u3[3];
-    int rc = mppi_step_batched(ctx->gbatch, q0, dU, &seed, &step, u3, &valid, 1);
+    int rc = mppi_step_batched(ctx->gbatch, q0, dU, &seed, &step, u3, &valid, use_graph);
     if (rc == MPPI_E_STATE) {
         if ((rc = mppi_batch_refresh(ctx->gbatch)) == MPPI_OK)
-            rc = mppi_step_batched(ctx->gbatch, q0, dU, &seed, &step, u3, &valid, 1);
+            rc = mppi_step_batched(ctx->gbatch, q0, dU, &seed, &step, u3, &valid, use_graph);
     }
     if (rc) return fail(ctx, rc, "graph mode: %s", mppi_batch_last_error(ctx->gbatch));
+    if (ctx->prof) {
+        double ms = 0.0;
+        long long n = 0;
+        if ((rc = mppi_batch_get_profile(ctx->gbatch, &ms, &n)) != MPPI_OK ||
+            (rc = mppi_batch_set_profiling(ctx->gbatch, 0)) != MPPI_OK)
+            return fail(ctx, rc, "graph mode: %s", mppi_batch_last_error(ctx->gbatch));
+        ctx->prof_ms += ms;
+        ctx->prof_n += n;
+    }
     for (int c = 0; c < prm->nu; ++c) u_out[c] = u3[c];
     if (valid_out) *valid_out = valid;
     return MPPI_OK;
@@ -352,7 +367,7 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
     if (!q0 || !dU || !u_out) return fail(ctx, MPPI_E_ARG, "NULL argument");
     if (int rc = check_params(ctx, prm)) return rc;
     DeviceGuard g(ctx->device);
-    if (ctx->graph_mode && !diag && !ctx->prof)
+    if (ctx->graph_mode && !diag)
         return step_via_graph(ctx, prm, q0, dU, seed, step, u_out, valid_out);
     const StepArgs A = make_args(ctx, prm, q0, seed, step);
     const mppi_diag D = diag ? *diag : mppi_diag{};

@@ -21,7 +21,8 @@ struct mppi_batch_s {
     std::vector<int> snap_n;
     std::vector<const void*> snap_ptr;
     // plan
-    double work_per_item = 0.0;     // target point-primitive pairs per queue item
+    double work_target = 0.0;       // requested pairs per queue item (0: default)
+    double work_per_item = 0.0;     // point-primitive pairs per queue item of the plan
     int resident[2][DMIN_CLASSES] = {};  // resident workgroups of each persistent launch
     std::vector<SceneBufs> bufs;
     std::vector<SceneDmin> sdm;     // [pass][scene]
@@ -115,10 +116,15 @@ bool snapshot_matches(mppi_batch b) {
 
 // Build the work queue for a given target work per item, size and carve the
 // workspace arena, and upload the static tables.
-int plan(mppi_batch b, double work_per_item) {
+constexpr double DEFAULT_WORK_PER_ITEM = 4194304.0;
+constexpr double MIN_WORK_PER_ITEM = 65536.0;
+
+// Plan for queue items of `work_target` point-primitive pairs (0: the
+// default, shrunk for small batches).
+int plan(mppi_batch b, double work_target) {
     drop_graph(b);
     const int n = b->n;
-    b->work_per_item = work_per_item;
+    b->work_target = work_target;
     b->bufs.assign(n, SceneBufs{});
     b->sdm.assign(2 * n, SceneDmin{});
     for (auto& p : b->items)
@@ -143,9 +149,9 @@ int plan(mppi_batch b, double work_per_item) {
     std::vector<size_t> off(n * 9);
     size_t total = 0;
     std::vector<int> nchunk(n), chunk(n), nchunk_nom(n), chunk_nom(n);
-    // small batches: shrink the items so that the sampled-rollout pass still
-    // has about two rounds of resident workgroups (work_per_item is a target
-    // for large batches, where LPT balance needs few, big items)
+    // default items: large for large batches (LPT balance needs few, big
+    // items), shrunk for small batches so that the sampled-rollout pass
+    // still has about two rounds of resident workgroups
     double total_pairs = 0.0;
     for (int s = 0; s < n; ++s) {
         const mppi_params& P = b->prms[s];
@@ -154,7 +160,16 @@ int plan(mppi_batch b, double work_per_item) {
         total_pairs += static_cast<double>(b->args[s].Kpad) * P.T * std::max(c->n_points, 0) * padded;
     }
     const int slots = *std::max_element(b->resident[0], b->resident[0] + DMIN_CLASSES);
-    work_per_item = std::max(65536.0, std::min(work_per_item, total_pairs / (2.0 * slots)));
+    const double work_per_item =
+        work_target > 0.0 ? std::max(MIN_WORK_PER_ITEM, work_target)
+                          : std::max(MIN_WORK_PER_ITEM,
+                                     std::min(DEFAULT_WORK_PER_ITEM, total_pairs / (2.0 * slots)));
+    b->work_per_item = work_per_item;
+    // validation pass (T poses per scene, one 128-lane tile): split each
+    // scene's points so that all scenes together give about two rounds of
+    // resident workgroups (chunks of at least 16 points)
+    const int val_slots = *std::max_element(b->resident[1], b->resident[1] + DMIN_CLASSES);
+    const int val_chunks = std::max(1, 2 * val_slots / std::max(n, 1));
     for (int s = 0; s < n; ++s) {
         const mppi_params& P = b->prms[s];
         mppi_ctx c = b->scenes[s];
@@ -170,7 +185,7 @@ int plan(mppi_batch b, double work_per_item) {
         nchunk[s] = std::max(1, (npts + ck - 1) / ck);
         chunk[s] = std::max(1, (npts + nchunk[s] - 1) / nchunk[s]);
         // validation pass: the T poses in one 128-lane tile, small chunks
-        const int ckn = std::max(32, (npts + 63) / 64);
+        const int ckn = std::max(16, (npts + val_chunks - 1) / val_chunks);
         nchunk_nom[s] = std::max(1, (npts + ckn - 1) / ckn);
         chunk_nom[s] = std::max(1, (npts + nchunk_nom[s] - 1) / nchunk_nom[s]);
         const size_t sizes[9] = {sizeof(float) * T * nu * Kpad, sizeof(float4) * T * Kpad,
@@ -418,7 +433,7 @@ int mppi_batch_create(mppi_batch* out, const mppi_ctx* scenes, const mppi_params
         return bfail(nullptr, MPPI_E_HIP, "batch setup: %s", hipGetErrorString(e));
     }
     // default plan: about 2^22 point-primitive pairs per queue item
-    if (int rc = plan(b, 4194304.0)) {
+    if (int rc = plan(b, 0.0)) {
         std::string m = b->err;
         mppi_batch_destroy(b);
         return bfail(nullptr, rc, "%s", m.c_str());
@@ -459,7 +474,15 @@ int mppi_batch_u_offsets(mppi_batch b, int* offsets) {
 int mppi_batch_refresh(mppi_batch b) {
     if (!b) return MPPI_E_ARG;
     DeviceGuard g(b->device);
-    return plan(b, b->work_per_item);
+    return plan(b, b->work_target);
+}
+
+int mppi_batch_set_work(mppi_batch b, double work_per_item) {
+    if (!b) return MPPI_E_ARG;
+    if (!(work_per_item >= 0.0) || work_per_item > 1e15)
+        return bfail(b, MPPI_E_ARG, "work_per_item must be >= 0 and finite");
+    DeviceGuard g(b->device);
+    return plan(b, work_per_item);
 }
 
 int mppi_step_batched(mppi_batch b, const float* q0, float* dU, const uint64_t* seeds,
@@ -513,13 +536,15 @@ int mppi_batch_autotune(mppi_batch b, int reps, double* out_work_per_item) {
     hipEvent_t e0, e1;
     BHIP(b, hipEventCreate(&e0));
     BHIP(b, hipEventCreate(&e1));
-    double best_w = b->work_per_item;
-    float best_ms = 1e30f;
+    // candidates: 2^16 .. 2^26 pairs per item
+    std::vector<double> cand;
+    for (int lg = 16; lg <= 26; ++lg) cand.push_back(std::ldexp(1.0, lg));
+    std::vector<float> best(cand.size(), 1e30f);
     int rc = MPPI_OK;
-    for (int lg = 18; lg <= 26 && rc == MPPI_OK; ++lg) {
-        const double w = std::ldexp(1.0, lg);
-        rc = plan(b, w);
-        if (rc) break;
+    // time `launches` passes of plan w (rollout poses regenerated per plan);
+    // returns the mean of all but the first launch
+    auto time_plan = [&](double w, int launches, float* mean_ms) -> int {
+        if (int r = plan(b, w)) return r;
         fill_steps(b, zeros.data(), dU.as<float>(), seeds.data(), stepv.data());
         hipError_t e = hipMemcpyAsync(b->d_steps.p, b->h_steps, sizeof(SceneStep) * b->n,
                                       hipMemcpyHostToDevice, b->stream);
@@ -527,34 +552,44 @@ int mppi_batch_autotune(mppi_batch b, int reps, double* out_work_per_item) {
             e = launch_rollout_batched(b->d_steps.as<SceneStep>(), b->d_bufs.as<SceneBufs>(),
                                        b->d_blk_roll.as<int2>(), static_cast<int>(b->blk_roll.size()),
                                        b->stream);
-        if (e != hipSuccess) {
-            rc = bfail(b, MPPI_E_HIP, "autotune: %s", hipGetErrorString(e));
-            break;
-        }
-        float ms_total = 0.f;
-        for (int k = 0; k <= reps && rc == MPPI_OK; ++k) {
+        if (e != hipSuccess) return bfail(b, MPPI_E_HIP, "autotune: %s", hipGetErrorString(e));
+        float total = 0.f;
+        for (int k = 0; k < launches; ++k) {
             e = launch_batch_reset(b->d_counters.as<int>(), 2 * DMIN_CLASSES, b->stream);
             if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-            if (e == hipSuccess) rc = launch_dmin_pass(b, 0);
-            if (e == hipSuccess && rc == MPPI_OK) e = hipEventRecord(e1, b->stream);
-            if (e == hipSuccess && rc == MPPI_OK) e = hipEventSynchronize(e1);
+            if (e != hipSuccess) return bfail(b, MPPI_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+            if (int r = launch_dmin_pass(b, 0)) return r;
+            e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
-            if (e == hipSuccess && rc == MPPI_OK) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) rc = bfail(b, MPPI_E_HIP, "autotune timing: %s", hipGetErrorString(e));
-            if (k > 0) ms_total += ms;  // the first launch is a warm-up
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) return bfail(b, MPPI_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+            if (k > 0) total += ms;  // the first launch is a warm-up
         }
-        if (rc) break;
-        if (ms_total / reps < best_ms) {
-            best_ms = ms_total / reps;
-            best_w = w;
+        *mean_ms = launches > 1 ? total / (launches - 1) : 0.f;
+        return MPPI_OK;
+    };
+    // warm the clocks up on the default plan, then time every candidate in a
+    // forward and a backward sweep and keep each one's faster sweep, so
+    // clock ramps do not favour the later candidates
+    float warm = 0.f;
+    rc = time_plan(0.0, 8, &warm);
+    for (int sweep = 0; sweep < 2 && rc == MPPI_OK; ++sweep)
+        for (size_t n = 0; n < cand.size() && rc == MPPI_OK; ++n) {
+            const size_t ci = sweep == 0 ? n : cand.size() - 1 - n;
+            float ms = 0.f;
+            rc = time_plan(cand[ci], reps + 1, &ms);
+            if (rc == MPPI_OK) best[ci] = std::min(best[ci], ms);
         }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     dU.release();
     if (rc) return rc;
-    if (int r2 = plan(b, best_w)) return r2;
-    if (out_work_per_item) *out_work_per_item = best_w;
+    size_t bi = 0;
+    for (size_t ci = 1; ci < cand.size(); ++ci)
+        if (best[ci] < best[bi]) bi = ci;
+    if (int r2 = plan(b, cand[bi])) return r2;
+    if (out_work_per_item) *out_work_per_item = cand[bi];
     return MPPI_OK;
 }
 

@@ -161,11 +161,24 @@ def test_batch_autotune_and_refresh(pkg):
     U1 = b.new_nominals()
     u1, v1 = b.mppi_step_batched(q0, U1, seeds, steps, use_graph=True)
     w = b.mppi_batch_autotune(reps=1)
-    assert 2 ** 18 <= w <= 2 ** 26
+    assert 2 ** 16 <= w <= 2 ** 26
+    assert b.mppi_batch_info()[2] == w
     U2 = b.new_nominals()
     u2, v2 = b.mppi_step_batched(q0, U2, seeds, steps, use_graph=True)
     np.testing.assert_array_equal(u1, u2)
     assert torch.equal(U1, U2)
+    # any fixed item size gives the same bits; below 2^16 pairs is raised to it
+    for work in (1.0, 3e5, 5e7, 0.0):
+        b.mppi_batch_set_work(work)
+        assert b.mppi_batch_info()[2] >= 2 ** 16
+        U3 = b.new_nominals()
+        u3, _ = b.mppi_step_batched(q0, U3, seeds, steps, use_graph=False)
+        np.testing.assert_array_equal(u1, u3)
+        assert torch.equal(U1, U3)
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(pkg.MppiError) as e:
+            b.mppi_batch_set_work(bad)
+        assert e.value.code == pkg.MPPI_E_ARG
     # changing a scene's points without re-planning is refused
     sc = cases[0][1]
     ctxs[0].set_points(sc["ox"][:100], sc["oy"][:100])

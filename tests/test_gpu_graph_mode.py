@@ -65,3 +65,28 @@ def test_graph_mode_equals_eager(pkg, name):
     graph.mppi_set_graph(False)
     eager.close()
     graph.close()
+
+
+def test_graph_mode_profiling_times_the_batch(pkg):
+    """With profiling on, graph mode runs its one-scene batch eagerly (same
+    bits as the replay) and reports one timed distance pass per step."""
+    import torch
+    prm, sc = scenes.config("c1", K=256, T=20)
+    a, b = _ctx(pkg, sc), _ctx(pkg, sc)
+    a.mppi_set_graph(True)
+    b.mppi_set_graph(True)
+    Ua = torch.zeros((prm["T"], prm["nu"]), device="cuda")
+    Ub = torch.zeros_like(Ua)
+    q = np.zeros(3, np.float32)
+    b.mppi_set_profiling(True)
+    for t in range(3):
+        ua, va, _ = a.mppi_step(prm, q, Ua, 4, t)
+        ub, vb, _ = b.mppi_step(prm, q, Ub, 4, t)
+        np.testing.assert_array_equal(ua, ub)
+        assert va == vb
+        assert torch.equal(Ua, Ub)
+    ms, n = b.mppi_get_profile()
+    assert n == 3 and ms > 0.0
+    b.mppi_set_profiling(False)
+    a.close()
+    b.close()
