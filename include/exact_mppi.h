@@ -269,9 +269,11 @@ MPPI_API int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, fl
  * set, time every candidate (workgroup size in {64, 128, 256} poses, number of
  * point chunks) on one sampled step with HIP events (reps launches each) and
  * keep the fastest for this context; mppi_step then uses it whenever the
- * shape (kind, padded primitive count, moving points, K*T, N) matches.
- * out_block / out_nchunk (host, may be NULL) receive the choice.  Results do
- * not depend on the choice (bit-identical).  Synchronous.                  */
+ * shape (kind, padded primitive count, moving points, K*T, N) matches.  With
+ * prm->validate the point-chunk count of the validation pass (T poses) is
+ * tuned the same way.  out_block / out_nchunk (host, may be NULL) receive
+ * the sampled pass's choice.  Results do not depend on the choice
+ * (bit-identical).  Synchronous.                                            */
 MPPI_API int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block,
                            int* out_nchunk);
 

@@ -484,10 +484,48 @@ int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block
             best_b = cand[ci].first;
             best_c = cand[ci].second;
         }
+    if (rc == MPPI_OK)
+        ctx->tuned[std::make_tuple(kind, padded, ctx->moving ? 1 : 0, npose, ctx->n_points)] = {best_b, best_c};
+    // the validation pass (T poses of the nominal, one 64-lane workgroup per
+    // point chunk): its chunk count, timed on the first T sampled poses
+    if (rc == MPPI_OK && prm->validate) {
+        const int nchunks[] = {8, 16, 32, 64, 128, 256, 512, 1024};
+        std::vector<int> vc;
+        for (int nc : nchunks)
+            if (nc == 8 || ctx->n_points / nc >= 8) vc.push_back(nc);
+        std::vector<float> vbest(vc.size(), 1e30f);
+        const PoseTime ptn{1, A.T, A.state_offset, A.dt};
+        HIP_TRY(ctx, ctx->key_nom.ensure(sizeof(unsigned int) * A.T));
+        unsigned int* vkey = ctx->key_nom.as<unsigned int>();
+        for (int sweep = 0; sweep < 2 && rc == MPPI_OK; ++sweep)
+            for (size_t n = 0; n < vc.size() && rc == MPPI_OK; ++n) {
+                const size_t ci = sweep == 0 ? n : vc.size() - 1 - n;
+                rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), A.T, ptn, kind, vkey, nullptr, 64, vc[ci]);
+                if (rc) break;
+                hipError_t e = hipEventRecord(e0, ctx->stream);
+                for (int k = 0; k < reps && rc == MPPI_OK; ++k)
+                    rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), A.T, ptn, kind, vkey, nullptr, 64,
+                                  vc[ci]);
+                if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc = fail(ctx, MPPI_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+                    break;
+                }
+                vbest[ci] = std::min(vbest[ci], ms / reps);
+            }
+        if (rc == MPPI_OK) {
+            size_t bi = 0;
+            for (size_t ci = 1; ci < vc.size(); ++ci)
+                if (vbest[ci] < vbest[bi]) bi = ci;
+            ctx->tuned[std::make_tuple(kind, padded, ctx->moving ? 1 : 0, A.T, ctx->n_points)] = {64, vc[bi]};
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    ctx->tuned[std::make_tuple(kind, padded, ctx->moving ? 1 : 0, npose, ctx->n_points)] = {best_b, best_c};
     if (out_block) *out_block = best_b;
     if (out_nchunk) *out_nchunk = best_c;
     return MPPI_OK;
