@@ -162,13 +162,13 @@ struct DminItem {
 // persistent kernel, each compiled for the occupancy its largest bucket
 // allows without spilling in the point loop: 0 polygons of 3..8 vertices
 // (6 waves per SIMD), 1 polygons of 9..16 (4 waves), 2 polygons padded to
-// 18..28 with a lane pair per pose (4 waves), 3 polygons padded to 30..32
-// with a lane pair per pose (3 waves), 4 rectangle covers up to 12 boxes
-// (8 waves), 5 larger covers (2 waves).
+// 18..30 with a lane pair per pose (4 waves), 3 polygons padded to 32 with a
+// lane pair per pose (3 waves), 4 rectangle covers up to 12 boxes (8
+// waves), 5 larger covers (2 waves).
 constexpr int DMIN_CLASSES = 6;
 inline int dmin_class(int kind, int padded) {
     if (kind == 1) return padded <= 12 ? 4 : 5;
-    return padded <= 8 ? 0 : padded <= 16 ? 1 : padded <= 28 ? 2 : 3;
+    return padded <= 8 ? 0 : padded <= 16 ? 1 : padded <= 30 ? 2 : 3;
 }
 constexpr bool dmin_class_pair(int cls) { return cls == 2 || cls == 3; }
 

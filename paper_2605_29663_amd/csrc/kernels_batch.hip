@@ -94,11 +94,11 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
             EMPPI_PAIR(24)
             EMPPI_PAIR(26)
             EMPPI_PAIR(28)
+            EMPPI_PAIR(30)
         default: break;
         }
     } else if (CLS == 3) {
         switch (S.padded) {
-            EMPPI_PAIR(30)
             EMPPI_PAIR(32)
         default: break;
         }

@@ -20,7 +20,7 @@ def pkg():
 
 
 def _mixed_scenes():
-    """Eleven small scenes covering every register class of the persistent
+    """Twelve small scenes covering every register class of the persistent
     kernel (small, medium and lane-pair polygons, odd and even vertex counts,
     static and moving points, small and large rectangle covers), all motion
     models and a scene without validation."""
@@ -65,6 +65,9 @@ def _mixed_scenes():
     p11 = scenes.params("c3", K=66, T=5, footprint_kind=0, goal=(0.5, -2.0))
     s11 = {k: (v[:600] if isinstance(v, np.ndarray) and v.ndim == 1 else v) for k, v in s3.items()}
     out.append((p11, dict(s11, polygon=scenes.star_polygon(rng, 13), rects=None)))
+    p12 = scenes.params("c1", K=64, T=5, goal=(1.5, 1.5))          # lane pairs, 30 padded
+    out.append((p12, dict(ox=pts[:400, 0].copy(), oy=pts[:400, 1].copy(),
+                          polygon=scenes.star_polygon(rng, 29), rects=None)))
     return out
 
 
