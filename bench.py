@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "hybrid", "cloud", "exp1"],
+                    choices=["c1", "c2", "c3", "c4", "hybrid", "cloud", "exp1", "proposal"],
                     help="c1/c2/c3: single-scene step; c4: 64-scene batched step (graph); "
                          "hybrid: three-mode cycle (Algorithm 2); cloud: point-cloud downsampling; "
                          "exp1: point-wise polygon vs rectangle-cover evaluator (L, T, F shapes)")
@@ -150,6 +150,100 @@ def run_hybrid(args):
         "config": {"workload": "hybrid modes (dual-Ackermann, parallel, spin) on the corridor",
                    "modes": 3, "K_per_mode": 1024, "T": T, "N": N, "B": B}}))
     h.close()
+
+
+def run_proposal(args):
+    """Learned proposal against plain MPPI on held-out corridor scenes (the
+    proposal's training workload): latency of one plain K = 4096 step, one
+    plain K = 1024 step and one learned cycle (features, the network's mean,
+    the fallback test on the two noise-free costs, the K = 1024 step), and the
+    network's training step (batch 1024, forward + backward + Adam on the
+    matrix cores).  The cost side of the comparison is the held-out
+    evaluation in profiles/proposal_c2_eval.json."""
+    import numpy as np
+    import torch
+    import paper_2605_29663_amd as pkg
+    from paper_2605_29663_amd import learn
+
+    net = pkg.Proposal(40, 2, hidden=256, max_batch=1024)
+    net.load(os.path.join(ROOT, "paper_2605_29663_amd", "proposal_c2.bin"))
+    scs = [learn.corridor_scene(learn.HELDOUT_SEED0 + s) for s in range(4)]
+    ctxs = [learn.make_context(sc) for sc in scs]
+    q = np.zeros(3, np.float32)
+    T = 40
+
+    def time_calls(fn, n):
+        for i in range(max(1, args.warmup)):
+            fn(i)
+        torch.cuda.synchronize()
+        lat = []
+        for i in range(n):
+            ts = time.perf_counter()
+            fn(10 ** 4 + i)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ts)
+        return float(np.mean(lat) * 1e3), float(np.percentile(lat, 50) * 1e3)
+
+    res = {}
+    for name, K in (("plain_k4096", 4096), ("plain_k1024", 1024)):
+        ms = []
+        for sc, c in zip(scs, ctxs):
+            prm = learn.scene_params(sc, K)
+            U = torch.zeros((T, 2), device="cuda")
+            ms.append(time_calls(lambda i: c.mppi_step(prm, q, U, 7, i), args.steps))
+        res[name] = (float(np.mean([m[0] for m in ms])), float(np.mean([m[1] for m in ms])))
+    ms = []
+    fallbacks = 0
+    for sc, c in zip(scs, ctxs):
+        prm = learn.scene_params(sc, 1024)
+        U = torch.zeros((T, 2), device="cuda")
+
+        def cycle(i):
+            nonlocal fallbacks
+            _, _, _, fb = learn.learned_update(net, c, prm, q, U, 7, 1024, step=i, diag=False)
+            fallbacks += int(fb)
+        ms.append(time_calls(cycle, args.steps))
+    res["learned_k1024"] = (float(np.mean([m[0] for m in ms])), float(np.mean([m[1] for m in ms])))
+
+    # training step: batch 1024 of features and targets
+    rng = np.random.default_rng(3)
+    feat = torch.tensor(rng.uniform(0, 1, (1024, net.in_dim)).astype(np.float32), device="cuda")
+    tgt = torch.tensor(rng.normal(0, 1, (1024, net.out_dim)).astype(np.float32), device="cuda")
+    for i in range(5):
+        net.train_step(feat, tgt, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    n_train = max(20, args.steps)
+    t0 = time.perf_counter()
+    for i in range(n_train):
+        net.train_step(feat, tgt, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3 / n_train
+    H, I, O, M = 256, net.in_dim, net.out_dim, 1024
+    mac_fwd = M * (I * H + H * H + H * O)
+    # backward: dW of all three layers, dX of the two upper layers
+    mac_bwd = M * (I * H + H * H + H * O) + M * (H * H + H * O)
+    train_tflops = 2.0 * (mac_fwd + mac_bwd) / (train_ms / 1e3) / 1e12
+    ev = json.load(open(os.path.join(ROOT, "profiles", "proposal_c2_eval.json")))
+    print(json.dumps({
+        "metric": "learned-proposal cycle latency (K=1024 + network) vs plain MPPI K=4096",
+        "value": res["learned_k1024"][0], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["learned_k1024"][0],
+        "latency_ms": {"p50": res["learned_k1024"][1]},
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (network), f32",
+        "data": "synthetic (seeded held-out corridor scenes)",
+        "config": {"workload": "learned proposal on corridor scenes", "T": T,
+                   "scenes": len(scs), "N": int(np.mean([sc["ox"].size for sc in scs]))},
+        "plain_k4096_ms": res["plain_k4096"][0], "plain_k1024_ms": res["plain_k1024"][0],
+        "speedup_vs_plain_k4096": res["plain_k4096"][0] / res["learned_k1024"][0],
+        "fallbacks": fallbacks,
+        "held_out_cost_ratio_learned_k1024_over_plain_k4096": ev["learned_small_over_plain_big"],
+        "mlp_train_step": {"batch": M, "ms": train_ms, "achieved": train_tflops,
+                           "peak": 2500.0, "unit": "TFLOP/s (bf16 MFMA)",
+                           "frac": train_tflops / 2500.0, "bound": "mfma (latency-bound at this size)"},
+    }))
+    net.close()
+    for c in ctxs:
+        c.close()
 
 
 def run_cloud(args):
@@ -324,6 +418,9 @@ def main():
         return
     if args.config == "cloud":
         run_cloud(args)
+        return
+    if args.config == "proposal":
+        run_proposal(args)
         return
     if args.config == "exp1":
         run_exp1(args)

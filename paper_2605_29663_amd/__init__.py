@@ -358,6 +358,8 @@ class Context:
 
     def mppi_step(self, prm, q0, U, seed, step, diag=False, params=None):
         """One control cycle.  U (T, nu) device float32 is updated in place.
+        diag: False, True (every diagnostic output) or a collection of
+        MppiDiag field names (only those are produced).
 
         Returns (u_star ndarray, valid bool, diag dict or None).
         """
@@ -379,7 +381,9 @@ class Context:
                        U_upd=torch.empty((T, nu), device=dev),
                        d_nom=torch.full((T,), math.nan, device=dev),
                        J_nom=torch.full((1,), math.nan, device=dev))
-            D = MppiDiag(*[out[k].data_ptr() for k in MppiDiag.names()])
+            if diag is not True:
+                out = {k: v for k, v in out.items() if k in set(diag)}
+            D = MppiDiag(*[out[k].data_ptr() if k in out else None for k in MppiDiag.names()])
         q = (ctypes.c_float * 3)(*[float(v) for v in q0])
         u_out = (ctypes.c_float * 3)()
         valid = ctypes.c_int(0)

@@ -193,31 +193,57 @@ __global__ void k_mse_grad(const float* __restrict__ out, const float* __restric
         dout_b[o] = to_bf16(d);
         acc += e * e;
     }
-    // fixed-order block sum
+    // fixed-order block sum (binary tree; blockDim.x is 256)
     __shared__ float sh[256];
     sh[threadIdx.x] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float s = 0.f;
-        for (int k = 0; k < static_cast<int>(blockDim.x); ++k) s += sh[k];
-        row_sq[m] = s;
+    for (int w = 128; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) row_sq[m] = sh[0];
 }
 
-__global__ void k_loss_sum(const float* __restrict__ row_sq, int M, int n_out, float* __restrict__ loss) {
-    if (threadIdx.x != 0) return;
+// Loss = sum of the row sums / (M n_out), fixed order: thread t adds rows
+// t, t + 1024, ... in turn, then a fixed binary tree over the 1024 partials.
+constexpr int LOSS_THREADS = 1024;
+
+__global__ __launch_bounds__(LOSS_THREADS) void k_loss_sum(const float* __restrict__ row_sq, int M,
+                                                           int n_out, float* __restrict__ loss) {
+    __shared__ float sh[LOSS_THREADS];
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += row_sq[m];
-    *loss = s / (static_cast<float>(M) * static_cast<float>(n_out));
+    for (int m = threadIdx.x; m < M; m += LOSS_THREADS) s += row_sq[m];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = LOSS_THREADS / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = sh[0] / (static_cast<float>(M) * static_cast<float>(n_out));
 }
 
-// Column sums over the batch (bias gradients), fixed order.
-__global__ void k_colsum(const float* __restrict__ d, int M, int N, float* __restrict__ out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// Column sums over the batch (bias gradients), fixed order: a block holds
+// 64 columns (one per lane) and COLSUM_GROUPS row groups (one per wave);
+// group g adds rows g, g + COLSUM_GROUPS, ... in turn, and the group
+// partials are added in group order.
+constexpr int COLSUM_GROUPS = 16;
+
+__global__ __launch_bounds__(64 * COLSUM_GROUPS) void k_colsum(const float* __restrict__ d, int M, int N,
+                                                               float* __restrict__ out) {
+    __shared__ float sh[COLSUM_GROUPS][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += d[static_cast<size_t>(m) * N + n];
-    out[n] = s;
+    if (n < N)
+        for (int m = g; m < M; m += COLSUM_GROUPS) s += d[static_cast<size_t>(m) * N + n];
+    sh[g][lane] = s;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float t = sh[0][lane];
+#pragma unroll
+        for (int k = 1; k < COLSUM_GROUPS; ++k) t += sh[k][lane];
+        out[n] = t;
+    }
 }
 
 // ---------------------------------------------------------------- Adam
@@ -312,12 +338,12 @@ hipError_t launch_mse_grad(const float* out, const float* tgt, int M, int n_out,
     hipLaunchKernelGGL(k_mse_grad, dim3(M), dim3(256), 0, s, out, tgt, M, n_out, dout, dout_b, row_sq);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, s, row_sq, M, n_out, loss);
+    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(LOSS_THREADS), 0, s, row_sq, M, n_out, loss);
     return hipGetLastError();
 }
 
 hipError_t launch_colsum(const float* d, int M, int N, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, s, d, M, N, out);
+    hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(64 * COLSUM_GROUPS), 0, s, d, M, N, out);
     return hipGetLastError();
 }
 

@@ -161,22 +161,25 @@ def nominal_cost(ctx, prm, q, U):
     """Noise-free augmented cost of one control sequence (K = 1, sigma = 0 rollout)."""
     p = dict(prm, K=1, sigma=(0.0, 0.0), validate=0)
     Uc = U.clone().contiguous()
-    _, _, D = ctx.mppi_step(p, q, Uc, 0, 0, diag=True)
+    _, _, D = ctx.mppi_step(p, q, Uc, 0, 0, diag=("J",))
     return float(D["J"][0].item())
 
 
-def learned_update(net, ctx, prm, q, U_shift, seed, K, step=0):
+def learned_update(net, ctx, prm, q, U_shift, seed, K, step=0, diag=True):
     """One MPPI update at K rollouts from the proposal's mean, or from the
     shifted nominal when the network's output is not finite or the mean's
-    noise-free cost is not lower.  Returns (u*, valid, diagnostics, fallback)."""
+    noise-free cost is not lower.  diag as in Context.mppi_step.  Returns
+    (u*, valid, diagnostics, fallback)."""
     net.set_scaling(prm)
     f = net.features(ctx, torch.tensor(np.asarray(q, np.float32)[None], device="cuda"),
                      U_shift[None].contiguous())
-    finite = bool(torch.isfinite(net.forward(f)).all())
     mu = net.mean(f)[0].contiguous()
+    # the raw network output of that same forward pass (the mean clamps to
+    # the control box, which would hide a non-finite output)
+    finite = bool(np.isfinite(net.get_buffer("out", net.out_dim)).all())
     fallback = not finite or not (nominal_cost(ctx, prm, q, mu) < nominal_cost(ctx, prm, q, U_shift))
     U = (U_shift if fallback else mu).clone().contiguous()
-    u, valid, D = ctx.mppi_step(dict(prm, K=K, validate=1), q, U, seed, step, diag=True)
+    u, valid, D = ctx.mppi_step(dict(prm, K=K, validate=1), q, U, seed, step, diag=diag)
     return u, valid, D, fallback
 
 
