@@ -236,6 +236,20 @@ MPPI_API int sdf_rectcover(mppi_ctx ctx, const float* dpx, const float* dpy, int
 MPPI_API int sdf_min_poses(mppi_ctx ctx, const float* dposes, int K, int T, float dt, int state_offset,
                   int kind, float* dd_min, int* dargmin);
 
+/* Noise-free augmented cost of n given control sequences from q0 (host, 3
+ * floats): each sequence (device dUseq, n*T*nu floats, sequence-major) is
+ * clamped to the control box, rolled out without noise and scored exactly as
+ * a sampled rollout of Algorithm 1 steps 1-2 is (J~ = sum over the horizon
+ * of phi_task + phi_ctrl + phi_obs, + w_inf when a distance falls below
+ * d_safe), against the footprint and points set.  dJ: device, n floats.
+ * prm supplies the model, horizon, costs and control box; its K, sigma and
+ * lambda are not used.  1 <= n <= MPPI_MAX_K (else MPPI_E_CAPACITY).
+ * Stream-ordered on the context's stream, no host synchronisation.  The
+ * cost of sequence U equals J~ of a one-rollout mppi_step around U with
+ * zero noise.                                                               */
+MPPI_API int mppi_sequence_costs(mppi_ctx ctx, const mppi_params* prm, const float* q0,
+                                 const float* dUseq, int n, float* dJ);
+
 /* Sampling and rollout only (Algorithm 1 step 1): K perturbed control
  * sequences around the nominal dU (device, T*nu row-major) and their Euler
  * rollouts from q0 (host, 3 floats).  Outputs (device, any may be NULL):

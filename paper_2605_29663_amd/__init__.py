@@ -26,7 +26,7 @@ MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
            "set_footprint", "set_points", "set_guidance", "cloud_downsample",
-           "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_rollout", "mppi_step",
+           "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_sequence_costs", "mppi_rollout", "mppi_step",
            "mppi_autotune", "mppi_tune_get", "mppi_tune_set", "mppi_set_tiles", "mppi_set_graph",
            "mppi_set_profiling", "mppi_get_profile",
            "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
@@ -110,6 +110,7 @@ def load():
     L.sdf_rectcover.argtypes = [vp, vp, vp, i, vp]
     L.sdf_min_poses.argtypes = [vp, vp, i, i, f, i, i, vp, vp]
     L.mppi_rollout.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp, vp, vp]
+    L.mppi_sequence_costs.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, i, vp]
     L.mppi_step.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(MppiDiag)]
     L.mppi_autotune.argtypes = [vp, ctypes.POINTER(MppiParams), i, ctypes.POINTER(i),
@@ -323,6 +324,19 @@ class Context:
         self._check(self.lib.mppi_rollout(self.h, ctypes.byref(p), q, _ptr(U), int(seed),
                                           int(step), _ptr(poses), _ptr(eps), _ptr(us)))
         return poses, eps, us
+
+    def mppi_sequence_costs(self, prm, q0, Useq):
+        """Noise-free augmented costs J~ of the control sequences Useq (n, T, nu)
+        from q0; returns a device tensor of n costs (stream-ordered)."""
+        p = make_params(prm)
+        Useq = _dev_f32(Useq, self.device, "Useq").contiguous()
+        n = Useq.numel() // (p.T * p.nu)
+        if n * p.T * p.nu != Useq.numel() or n < 1:
+            raise ValueError("Useq must hold n whole (T, nu) sequences")
+        J = torch.empty(n, dtype=torch.float32, device=self.device)
+        q = (ctypes.c_float * 3)(*[float(v) for v in q0])
+        self._check(self.lib.mppi_sequence_costs(self.h, ctypes.byref(p), q, _ptr(Useq), int(n), _ptr(J)))
+        return J
 
     def mppi_autotune(self, prm, reps=3, params=None):
         """Time the candidate tile shapes for prm's shape; returns (block, nchunk)."""

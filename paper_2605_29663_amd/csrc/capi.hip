@@ -21,7 +21,7 @@ using namespace emppi;
 using namespace emppi_host;
 
 static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
-                           float* deps, float* du, bool argmin);
+                           float* deps, float* du, bool argmin, const float* useq = nullptr);
 
 extern "C" {
 
@@ -268,7 +268,7 @@ int sdf_min_poses(mppi_ctx ctx, const float* dposes, int K, int T, float dt, int
 }
 
 static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
-                           float* deps, float* du, bool argmin) {
+                           float* deps, float* du, bool argmin, const float* useq) {
     const size_t Kpad = A.Kpad, T = A.T, nu = A.nu;
     HIP_TRY(ctx, ctx->eps_ws.ensure(sizeof(float) * T * nu * Kpad));
     HIP_TRY(ctx, ctx->poses_ws.ensure(sizeof(float4) * T * Kpad));
@@ -286,7 +286,31 @@ static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, flo
     o.diag_poses = dposes;
     o.diag_eps = deps;
     o.diag_u = du;
+    o.useq = useq;
     HIP_TRY(ctx, launch_rollout(A, dU, o, ctx->stream));
+    return MPPI_OK;
+}
+
+int mppi_sequence_costs(mppi_ctx ctx, const mppi_params* prm, const float* q0, const float* dUseq, int n,
+                        float* dJ) {
+    if (!ctx) return MPPI_E_ARG;
+    if (!prm || !q0 || !dUseq || !dJ) return fail(ctx, MPPI_E_ARG, "NULL argument");
+    if (n < 1 || n > MPPI_MAX_K) return fail(ctx, MPPI_E_CAPACITY, "n out of range");
+    mppi_params p = *prm;
+    p.K = n;
+    if (int rc = check_params(ctx, &p)) return rc;
+    DeviceGuard g(ctx->device);
+    const StepArgs A = make_args(ctx, &p, q0, 0, 0);
+    // rollouts of the given sequences (dU is not read in this mode)
+    if (int rc = rollout_into_ws(ctx, A, dUseq, nullptr, nullptr, nullptr, false, dUseq)) return rc;
+    const PoseTime pt{A.Kpad, A.T, A.state_offset, A.dt};
+    if (int rc = run_dmin(ctx, ctx->poses_ws.as<float4>(), A.T * A.Kpad, pt, p.footprint_kind,
+                          ctx->key.as<unsigned int>(), nullptr))
+        return rc;
+    HIP_TRY(ctx, ctx->jt.ensure(sizeof(float) * A.Kpad));
+    HIP_TRY(ctx, launch_cost(A, ctx->key.as<unsigned int>(), nullptr, ctx->jbase.as<float>(),
+                             ctx->jt.as<float>(), nullptr, nullptr, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(dJ, ctx->jt.p, sizeof(float) * n, hipMemcpyDeviceToDevice, ctx->stream));
     return MPPI_OK;
 }
 

@@ -92,7 +92,8 @@ hipError_t launch_compact_points(const float* x, const float* y, const float* vx
                                  float* ovx, float* ovy, int* oidx, int* n_valid, hipStream_t s);
 
 struct RolloutOut {
-    float* eps_ws;   // [T][nu][Kpad]
+    const float* useq = nullptr;  // [K][T][nu] given control sequences (no noise), or nullptr
+    float* eps_ws;   // [T][nu][Kpad] (may be nullptr with useq)
     float4* poses;   // [T][Kpad]
     float* jbase;    // [Kpad]
     unsigned int* key;          // [T][Kpad] distance keys to initialise (or nullptr)

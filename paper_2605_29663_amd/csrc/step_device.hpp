@@ -124,7 +124,14 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
         const int h = h0 + hh;
         if (hh < hn) {
             float u[3] = {0.f, 0.f, 0.f};
-            if (r < P.K) {
+            if (r < P.K && o.useq) {
+                // a given sequence, clamped to the control box, no noise
+                for (int k = 0; k < nu; ++k) {
+                    float v = o.useq[(static_cast<size_t>(r) * T + h) * nu + k];
+                    v = fmaxf(v, P.umin[k]);
+                    u[k] = fminf(v, P.umax[k]);
+                }
+            } else if (r < P.K) {
                 float z[4];
                 normals4(P.seed, P.step, static_cast<uint32_t>(r), static_cast<uint32_t>(h), P.stream, z);
                 for (int k = 0; k < nu; ++k) {

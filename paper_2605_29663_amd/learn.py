@@ -158,11 +158,9 @@ def train(net, X, Y, epochs=30, batch=1024, lr=1e-3, lr_final=1e-4, seed=0, log=
 
 
 def nominal_cost(ctx, prm, q, U):
-    """Noise-free augmented cost of one control sequence (K = 1, sigma = 0 rollout)."""
-    p = dict(prm, K=1, sigma=(0.0, 0.0), validate=0)
-    Uc = U.clone().contiguous()
-    _, _, D = ctx.mppi_step(p, q, Uc, 0, 0, diag=("J",))
-    return float(D["J"][0].item())
+    """Noise-free augmented cost of one control sequence (the J~ of a
+    zero-noise one-rollout step around it)."""
+    return float(ctx.mppi_sequence_costs(prm, q, U.reshape(1, *U.shape))[0].item())
 
 
 def learned_update(net, ctx, prm, q, U_shift, seed, K, step=0, diag=True):
@@ -177,7 +175,9 @@ def learned_update(net, ctx, prm, q, U_shift, seed, K, step=0, diag=True):
     # the raw network output of that same forward pass (the mean clamps to
     # the control box, which would hide a non-finite output)
     finite = bool(np.isfinite(net.get_buffer("out", net.out_dim)).all())
-    fallback = not finite or not (nominal_cost(ctx, prm, q, mu) < nominal_cost(ctx, prm, q, U_shift))
+    # the two noise-free costs in one call
+    J = ctx.mppi_sequence_costs(prm, q, torch.stack([mu, U_shift.reshape(mu.shape)])).cpu().numpy()
+    fallback = not finite or not (J[0] < J[1])
     U = (U_shift if fallback else mu).clone().contiguous()
     u, valid, D = ctx.mppi_step(dict(prm, K=K, validate=1), q, U, seed, step, diag=diag)
     return u, valid, D, fallback

@@ -460,3 +460,32 @@ def test_step_full_size_sampled(ctx, pkg, orc, name):
     u_star, valid, D = ctx.mppi_step(prm, q0, Ut, 0x5EED0002, 0, diag=True)
     sample = np.random.default_rng(0).choice(prm["K"] * prm["T"], 256, replace=False)
     _check_step_rows(orc, prm, sc, q0, U0, 0x5EED0002, 0, u_star, valid, D, Ut, sample=sample)
+
+
+def test_sequence_costs(ctx, pkg, orc):
+    """Noise-free costs of given control sequences (some outside the control
+    box): equal to the J~ of a zero-noise one-rollout step bit for bit, and to
+    the oracle's own rollout, distances and costs."""
+    import torch
+    prm, sc = scenes.config("c2", K=1, T=24)
+    sc = dict(sc, ox=sc["ox"][:2000], oy=sc["oy"][:2000])
+    _load_scene(ctx, pkg, prm, sc)
+    rng = np.random.default_rng(77)
+    n, T = 5, prm["T"]
+    lo, hi = np.float32(prm["u_min"][:2]), np.float32(prm["u_max"][:2])
+    Useq = rng.uniform(1.3 * lo, 1.3 * hi, (n, T, 2)).astype(np.float32)
+    q0 = np.float32([0.1, -0.05, 0.02])
+    J = _np(ctx.mppi_sequence_costs(prm, q0, torch.tensor(Useq, device="cuda")))
+    p0 = dict(prm, K=1, sigma=(0.0, 0.0), validate=0)
+    for r in range(n):
+        U = torch.tensor(Useq[r], device="cuda")
+        _, _, D = ctx.mppi_step(p0, q0, U, 0, 0, diag=("J",))
+        assert J[r] == _np(D["J"])[0]
+        poses, _, u = orc.rollout_f32(p0, q0, Useq[r], 0, 0)
+        d = orc.dmin(poses.reshape(-1, 4), orc.tau_of(p0, T), sc["ox"], sc["oy"], kind=0,
+                     geom=sc["polygon"]).reshape(1, T)
+        _, _, Jt = orc.costs(p0, poses[..., :2], u, d)
+        assert not np.any((np.abs(d) < TOL_D) | (np.abs(d - p0["d_safe"]) < TOL_D))
+        np.testing.assert_allclose(J[r], Jt[0], rtol=1e-5)
+    with pytest.raises(ValueError):
+        ctx.mppi_sequence_costs(prm, q0, torch.zeros((0, T, 2), device="cuda"))
