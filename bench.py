@@ -121,6 +121,7 @@ def run_hybrid(args):
     ctx.set_footprint(pkg.POLYGON, scenes.FOOTPRINT_RANGER6)
     ctx.set_points(sc["ox"], sc["oy"])
     h = pkg.Hybrid(ctx, modes)
+    work = h.autotune(reps=2)
     U = h.new_nominals()
     hp = dict(lambda_switch=2.0, cool_max=5, v_min=0.1, w_min=0.2, noise_v=0.01, noise_w=0.02)
     state = (0, 0)
@@ -148,7 +149,8 @@ def run_hybrid(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded scene generator)", "execution": "hipGraph replay",
         "config": {"workload": "hybrid modes (dual-Ackermann, parallel, spin) on the corridor",
-                   "modes": 3, "K_per_mode": 1024, "T": T, "N": N, "B": B}}))
+                   "modes": 3, "K_per_mode": 1024, "T": T, "N": N, "B": B,
+                   "pairs_per_item": work}}))
     h.close()
 
 

@@ -548,6 +548,14 @@ class Hybrid:
     def new_nominals(self):
         return torch.zeros(max(1, self.u_offsets[-1]), dtype=torch.float32, device=self.device)
 
+    def autotune(self, reps=2):
+        """Autotune the queue item size of the underlying batch (see
+        mppi_batch_autotune); returns the chosen pairs per item."""
+        w = ctypes.c_double()
+        self._check(self.lib.mppi_batch_autotune(self.lib.mppi_hybrid_batch(self.h), int(reps),
+                                                 ctypes.byref(w)))
+        return w.value
+
     def nominal(self, U, m):
         p = self.params[m]
         return U[self.u_offsets[m]:self.u_offsets[m + 1]].view(p.T, p.nu)

@@ -127,6 +127,7 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
     best = INFINITY;  // unreachable for planned items
 }
 
+// Waves per SIMD each register class is compiled for (its register budget).
 template <int CLS>
 constexpr int persistent_waves() {
     constexpr int waves[DMIN_CLASSES] = {6, 4, 4, 3, 8, 2};

@@ -164,3 +164,25 @@ def test_hybrid_argument_errors(pkg):
     with pytest.raises(pkg.MppiError):
         h.step(np.zeros(3), U, 0, 0, dict(HP, cool_max=-1), 0, 0)
     h.close()
+
+
+def test_hybrid_autotuned_equals_default(pkg):
+    """The autotuned queue item size changes no bit of the cycle."""
+    import torch
+    sc = _scene()
+    modes = _modes(tuple(float(g) for g in sc["goal"]))
+    q0 = np.float32([0.0, 0.05, 0.02])
+    res = []
+    for tune in (False, True):
+        c = _ctx(pkg, sc)
+        h = pkg.Hybrid(c, modes)
+        if tune:
+            assert 2 ** 16 <= h.autotune(reps=1) <= 2 ** 26
+        U = h.new_nominals()
+        r = h.step(q0, U, 11, 0, HP, 0, 0, use_graph=True)
+        res.append((r["u"], r["mode"], r["J"], U.cpu().numpy()))
+        h.close()
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1]
+    np.testing.assert_array_equal(res[0][2], res[1][2])
+    np.testing.assert_array_equal(res[0][3], res[1][3])
