@@ -153,13 +153,16 @@ int plan(mppi_batch b, double work_target) {
     // items), shrunk for small batches so that the sampled-rollout pass
     // still has about two rounds of resident workgroups
     double total_pairs = 0.0;
+    int slots = 1, val_slots = 1;  // resident workgroups of the classes this batch uses
     for (int s = 0; s < n; ++s) {
         const mppi_params& P = b->prms[s];
         mppi_ctx c = b->scenes[s];
         const int padded = P.footprint_kind == 0 ? c->BP : c->RP;
         total_pairs += static_cast<double>(b->args[s].Kpad) * P.T * std::max(c->n_points, 0) * padded;
+        const int cls = dmin_class(P.footprint_kind, padded);
+        slots = std::max(slots, b->resident[0][cls]);
+        val_slots = std::max(val_slots, b->resident[1][cls]);
     }
-    const int slots = *std::max_element(b->resident[0], b->resident[0] + DMIN_CLASSES);
     const double work_per_item =
         work_target > 0.0 ? std::max(MIN_WORK_PER_ITEM, work_target)
                           : std::max(MIN_WORK_PER_ITEM,
@@ -168,7 +171,6 @@ int plan(mppi_batch b, double work_target) {
     // validation pass (T poses per scene, one 128-lane tile): split each
     // scene's points so that all scenes together give about two rounds of
     // resident workgroups (chunks of at least 16 points)
-    const int val_slots = *std::max_element(b->resident[1], b->resident[1] + DMIN_CLASSES);
     const int val_chunks = std::max(1, 2 * val_slots / std::max(n, 1));
     for (int s = 0; s < n; ++s) {
         const mppi_params& P = b->prms[s];
