@@ -13,7 +13,8 @@ the step's wall time); `ms_per_step` is the step latency.  `roofline` reports
 the dominant kernel (fused transform + signed distance + min) against the
 VALU issue peak, timed with HIP events recorded on the library's stream
 around every launch of that kernel in the timed region.  `cpu_baseline` is the
-CPU oracle timed on a bounded sample of the same step.
+CPU oracle timed on a bounded sample of the same step, on all host threads
+(`value`, `cores`) and on one thread (`one_thread`), with the host CPU model.
 """
 from __future__ import annotations
 
@@ -58,6 +59,9 @@ def parse():
                     help="time steps replayed from a captured graph of a one-scene batch "
                          "(autotuned persistent distance kernel, timed on as many eager steps "
                          "of the same batch right after)")
+    ap.add_argument("--polygon-vertices", type=int, default=0,
+                    help="c1/c2: replace the footprint by a seeded star-shaped polygon of this "
+                         "many vertices (3..64; radii 0.15..0.4 m)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), "
                          "the reference kernel for scaling the HBM byte counters")
@@ -67,12 +71,24 @@ def parse():
 def padded_count(kind, count):
     """Primitive count the fused kernel is instantiated for (padding is exact)."""
     if kind == 0:
-        return max(3, count) if count <= 16 else (count + 1) // 2 * 2
+        if count <= 16:
+            return max(3, count)
+        return (count + 1) // 2 * 2 if count <= 32 else (count + 3) // 4 * 4
     return next(b for b in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32) if count <= b)
 
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_29663_amd", "csrc", f)
                   for f in ("kernels_sdf.hip", "kernels_batch.hip", "sdf_device.hpp", "kernels.hpp")]
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def kernel_sha256():
@@ -433,6 +449,11 @@ def main():
     from paper_2605_29663_amd import scenes
 
     prm, sc = scenes.config(args.config)
+    if args.polygon_vertices:
+        if prm["footprint_kind"] != 0:
+            sys.exit("--polygon-vertices applies to the polygon workloads (c1, c2)")
+        B = args.polygon_vertices
+        sc = dict(sc, polygon=scenes.star_polygon(np.random.default_rng(B), B, 0.15, 0.4))
     kind = prm["footprint_kind"]
     K, T, nu = prm["K"], prm["T"], prm["nu"]
     N = int(np.size(sc["ox"]))
@@ -513,15 +534,18 @@ def main():
         "data": "synthetic (seeded scene generator)",
         "execution": "hipGraph replay" if args.graph else "eager launches",
         "config": {"workload": {"c1": "unicycle open field", "c2": "ackermann corridor",
-                                "c3": "omni rectangle cover, moving points"}[args.config],
+                                "c3": "omni rectangle cover, moving points"}[args.config]
+                               + (f", star footprint of {P} vertices" if args.polygon_vertices else ""),
                    "K": K, "T": T, "N": N, ("B" if kind == 0 else "R"): P,
                    "motion_model": prm["model"], "dt": prm["dt"]},
         "roofline": {"bound": "alu",
                      "kernel": ("k_dmin_persistent (one-scene batch)" if args.graph else
-                                "k_dmin_poly" if kind == 0 else "k_dmin_rect"),
+                                "k_dmin_rect" if kind else
+                                "k_dmin_poly" if P <= 16 else "k_dmin_poly_part"),
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None if args.graph else traffic_record(workload),
+                     "traffic": (None if args.graph or args.polygon_vertices else
+                                 traffic_record(workload)),
                      "kernel_ms": k_avg_ms, "launches": k_n,
                      "tiles": ({"source": "batch autotuner (queue item size)"} if args.graph else
                                {"block": tuned[0], "chunks": tuned[1], "source": tile_source})},
@@ -535,11 +559,25 @@ def main():
         for k in range(reps):
             orc.mppi_step(prm, np.zeros(3, np.float32), np.zeros((T, nu), np.float32), sc, seed, k)
         cpu_s = time.perf_counter() - ts
+        n_threads = orc.num_threads()
+        # the same on one thread, over a bounded sample: one step with K / 16 rollouts
+        K1 = max(64, K // 16)
+        orc.set_num_threads(1)
+        ts = time.perf_counter()
+        orc.mppi_step(dict(prm, K=K1), np.zeros(3, np.float32), np.zeros((T, nu), np.float32), sc,
+                      seed, 0)
+        one_s = time.perf_counter() - ts
+        orc.set_num_threads(n_threads)
+        pairs_one = (K1 * T + (T if prm["validate"] else 0)) * N * P
         out["cpu_baseline"] = {"value": reps * pairs_step / cpu_s, "unit": "evals/s",
                                "ms_per_step": cpu_s * 1e3 / reps,
-                               "cores": orc.num_threads(), "kind": "oracle",
+                               "cores": n_threads, "kind": "oracle",
                                "sample": f"{reps} whole oracle steps of the same workload "
-                                         f"(K={K}, T={T}, N={N}, {P} primitives), {cpu_s:.1f} s"}
+                                         f"(K={K}, T={T}, N={N}, {P} primitives), {cpu_s:.1f} s",
+                               "one_thread": {"value": pairs_one / one_s, "unit": "evals/s",
+                                              "sample": f"one whole oracle step with K={K1} "
+                                                        f"(otherwise the same workload), {one_s:.1f} s"},
+                               "host_cpu": host_cpu_model(), "host_cpus": os.cpu_count()}
     print(json.dumps(out))
     ctx.close()
 

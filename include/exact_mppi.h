@@ -50,7 +50,7 @@ enum { MPPI_FP_POLYGON = 0, MPPI_FP_RECTS = 1 };
 enum { MPPI_UNICYCLE = 0, MPPI_ACKERMANN = 1, MPPI_OMNI = 2, MPPI_SPIN = 3, MPPI_PARALLEL = 4 };
 
 /* Capacities. */
-#define MPPI_MAX_B 32        /* polygon vertices */
+#define MPPI_MAX_B 64        /* polygon vertices */
 #define MPPI_MAX_R 32        /* rectangles in a cover */
 #define MPPI_MAX_T 128       /* horizon */
 #define MPPI_MAX_K (1 << 20) /* rollouts */

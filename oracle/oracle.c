@@ -575,6 +575,15 @@ EXPORT int orc_num_threads(void) {
 #endif
 }
 
+/* Set the number of threads of the OpenMP loops above (n >= 1). */
+EXPORT void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* ======================================================================== */
 /* Features of the learned proposal in the FP32 sequence (not part of the   */
 /* paper's method).  Every operation is one correctly rounded binary32      */

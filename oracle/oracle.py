@@ -87,6 +87,7 @@ def lib():
                                       vp, vp, vp]
         L.orc_rollout_nominal_f32.argtypes = [i, i, i, f, f, vp, vp, i, vp]
         L.orc_num_threads.restype = i
+        L.orc_set_num_threads.argtypes = [i]
         L.orc_f32_features.argtypes = [vp, vp, vp, l, vp, vp, vp, i, i, vp, vp, f, vp]
         _lib = L
     return _lib
@@ -94,6 +95,10 @@ def lib():
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 def _p(a):

@@ -179,14 +179,14 @@ int plan(mppi_batch b, double work_target) {
         const int padded = kind == 0 ? c->BP : c->RP;
         const size_t Kpad = b->args[s].Kpad, T = P.T, nu = P.nu;
         const int npts = std::max(c->n_points, 0);
-        // rollout pass: pose tiles of 256 lanes (128 poses where a lane pair
-        // shares a pose), chunks sized for the target work
+        // rollout pass: pose tiles of 256 lanes (fewer poses where a lane
+        // group shares a pose), chunks sized for the target work
         const double per_point = 256.0 / dmin_persistent_lanes_per_pose(dmin_class(kind, padded)) * padded;
         int ck = static_cast<int>(std::max(32.0, std::min(static_cast<double>(std::max(npts, 1)),
                                                           work_per_item / per_point)));
         nchunk[s] = std::max(1, (npts + ck - 1) / ck);
         chunk[s] = std::max(1, (npts + nchunk[s] - 1) / nchunk[s]);
-        // validation pass: the T poses in one 128-lane tile, small chunks
+        // validation pass: the T poses in tiles of 128 lanes, small chunks
         const int ckn = std::max(16, (npts + val_chunks - 1) / val_chunks);
         nchunk_nom[s] = std::max(1, (npts + ckn - 1) / ckn);
         chunk_nom[s] = std::max(1, (npts + nchunk_nom[s] - 1) / nchunk_nom[s]);

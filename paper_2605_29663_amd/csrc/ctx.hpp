@@ -274,7 +274,8 @@ inline PointArgs point_args(mppi_ctx ctx) {
 // estimate how many workgroups are resident at once.
 inline int dmin_waves_per_simd(int kind, int padded) {
     if (kind == 1) return 8;
-    // above 16 vertices a lane pair shares a pose (half the edges per lane)
+    // above 16 vertices a lane pair shares a pose (half the edges per lane),
+    // above 32 a lane quad
     return padded <= 8 ? 6 : padded <= 16 ? 4 : 3;
 }
 
@@ -283,7 +284,7 @@ inline int dmin_waves_per_simd(int kind, int padded) {
 // last round is not a nearly empty tail (all workgroups do equal work).
 inline void choose_tiles(int kind, int padded, int npose, int n_points, int& block, int& nchunk, int& chunk) {
     block = npose >= 4096 ? 256 : 64;
-    const int lanes = (kind == 0 && padded > 16) ? 2 : 1;  // lanes per pose
+    const int lanes = kind == 0 && padded > 32 ? 4 : kind == 0 && padded > 16 ? 2 : 1;  // per pose
     const int pose_blocks = std::max(1, (lanes * npose + block - 1) / block);
     const int resident = 256 * 4 * dmin_waves_per_simd(kind, padded) / (block / WAVE);
     // a pass over few poses (the validation rollout) is bound by the serial

@@ -165,13 +165,15 @@ struct DminItem {
 // (6 waves per SIMD), 1 polygons of 9..16 (4 waves), 2 polygons padded to
 // 18..30 with a lane pair per pose (4 waves), 3 polygons padded to 32 with a
 // lane pair per pose (3 waves), 4 rectangle covers up to 12 boxes (8
-// waves), 5 larger covers (2 waves).
-constexpr int DMIN_CLASSES = 6;
+// waves), 5 larger covers (2 waves), 6 polygons padded to 36..64 with a lane
+// quad per pose (3 waves).
+constexpr int DMIN_CLASSES = 7;
 inline int dmin_class(int kind, int padded) {
     if (kind == 1) return padded <= 12 ? 4 : 5;
-    return padded <= 8 ? 0 : padded <= 16 ? 1 : padded <= 30 ? 2 : 3;
+    return padded <= 8 ? 0 : padded <= 16 ? 1 : padded <= 30 ? 2 : padded <= 32 ? 3 : 6;
 }
-constexpr bool dmin_class_pair(int cls) { return cls == 2 || cls == 3; }
+// Lanes that share one pose in a register class.
+constexpr int dmin_class_lanes(int cls) { return cls == 2 || cls == 3 ? 2 : cls == 6 ? 4 : 1; }
 
 hipError_t launch_batch_reset(int* counters, int n, hipStream_t s);
 hipError_t launch_rollout_batched(const SceneStep* steps, const SceneBufs* bufs, const int2* blk,

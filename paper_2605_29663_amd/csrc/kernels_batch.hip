@@ -50,12 +50,12 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
         else                                                                                  \
             dmin_poly_range<P, false, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);  \
         return;
-#define EMPPI_PAIR(P)                                                                         \
+#define EMPPI_PART(P, L)                                                                      \
     case P:                                                                                   \
         if (moving)                                                                           \
-            dmin_poly_pair_range<P / 2, true>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi); \
+            dmin_poly_part_range<P / L, L, true>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);  \
         else                                                                                  \
-            dmin_poly_pair_range<P / 2, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi);\
+            dmin_poly_part_range<P / L, L, false>(q, tau, S.pts, c0, c1, S.verts, lds, best, bi); \
         return;
 #define EMPPI_RECT(P)                                                                         \
     case P:                                                                                   \
@@ -88,18 +88,30 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
         }
     } else if (CLS == 2) {
         switch (S.padded) {
-            EMPPI_PAIR(18)
-            EMPPI_PAIR(20)
-            EMPPI_PAIR(22)
-            EMPPI_PAIR(24)
-            EMPPI_PAIR(26)
-            EMPPI_PAIR(28)
-            EMPPI_PAIR(30)
+            EMPPI_PART(18, 2)
+            EMPPI_PART(20, 2)
+            EMPPI_PART(22, 2)
+            EMPPI_PART(24, 2)
+            EMPPI_PART(26, 2)
+            EMPPI_PART(28, 2)
+            EMPPI_PART(30, 2)
         default: break;
         }
     } else if (CLS == 3) {
         switch (S.padded) {
-            EMPPI_PAIR(32)
+            EMPPI_PART(32, 2)
+        default: break;
+        }
+    } else if (CLS == 6) {
+        switch (S.padded) {
+            EMPPI_PART(36, 4)
+            EMPPI_PART(40, 4)
+            EMPPI_PART(44, 4)
+            EMPPI_PART(48, 4)
+            EMPPI_PART(52, 4)
+            EMPPI_PART(56, 4)
+            EMPPI_PART(60, 4)
+            EMPPI_PART(64, 4)
         default: break;
         }
     } else if (CLS == 4) {
@@ -113,7 +125,7 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
             EMPPI_RECT(12)
         default: break;
         }
-    } else {
+    } else if (CLS == 5) {
         switch (S.padded) {
             EMPPI_RECT(16)
             EMPPI_RECT(24)
@@ -122,7 +134,7 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
         }
     }
 #undef EMPPI_POLY
-#undef EMPPI_PAIR
+#undef EMPPI_PART
 #undef EMPPI_RECT
     best = INFINITY;  // unreachable for planned items
 }
@@ -130,7 +142,7 @@ __device__ __forceinline__ void dmin_dispatch(const SceneDmin& S, bool moving, f
 // Waves per SIMD each register class is compiled for (its register budget).
 template <int CLS>
 constexpr int persistent_waves() {
-    constexpr int waves[DMIN_CLASSES] = {6, 4, 4, 3, 8, 2};
+    constexpr int waves[DMIN_CLASSES] = {6, 4, 4, 3, 8, 2, 3};
     return waves[CLS];
 }
 
@@ -151,8 +163,9 @@ void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __rest
         if (it >= n_items) break;
         const DminItem w = wave_uniform(items[it]);
         const SceneDmin S = wave_uniform(sds[w.sd]);
-        // lane-pair class: two lanes per pose
-        const int g = w.g0 + static_cast<int>(dmin_class_pair(CLS) ? threadIdx.x >> 1 : threadIdx.x);
+        // lane-group classes: dmin_class_lanes(CLS) lanes per pose
+        constexpr int L = dmin_class_lanes(CLS);
+        const int g = w.g0 + static_cast<int>(threadIdx.x / L);
         const int npose = S.npose;
         const bool live = g < npose;
         const float4 q = live ? S.poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
@@ -163,7 +176,7 @@ void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __rest
         const int c1 = min(c0 + S.chunk, nv);
         float best;
         dmin_dispatch<CLS>(S, moving, q, tau, c0, c1, lds, best);
-        if (live && (!dmin_class_pair(CLS) || (threadIdx.x & 1) == 0)) atomicMin(&S.key[g], dkey(best));
+        if (live && (threadIdx.x & (L - 1)) == 0) atomicMin(&S.key[g], dkey(best));
     }
 }
 
@@ -270,7 +283,7 @@ constexpr size_t PERSISTENT_LDS = static_cast<size_t>(DMIN_TILE) * 16;
 using PersistentKernel = void (*)(const SceneDmin*, const DminItem*, int, int*);
 constexpr PersistentKernel PERSISTENT[DMIN_CLASSES] = {
     k_dmin_persistent<0>, k_dmin_persistent<1>, k_dmin_persistent<2>, k_dmin_persistent<3>,
-    k_dmin_persistent<4>, k_dmin_persistent<5>};
+    k_dmin_persistent<4>, k_dmin_persistent<5>, k_dmin_persistent<6>};
 
 int dmin_persistent_blocks_per_cu(int cls, int block) {
     if (cls < 0 || cls >= DMIN_CLASSES) return 0;
@@ -279,7 +292,7 @@ int dmin_persistent_blocks_per_cu(int cls, int block) {
         &nb, reinterpret_cast<const void*>(PERSISTENT[cls]), block, PERSISTENT_LDS);
     return e == hipSuccess ? nb : 0;
 }
-int dmin_persistent_lanes_per_pose(int cls) { return dmin_class_pair(cls) ? 2 : 1; }
+int dmin_persistent_lanes_per_pose(int cls) { return dmin_class_lanes(cls); }
 
 hipError_t launch_batch_reset(int* counters, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counters, n);

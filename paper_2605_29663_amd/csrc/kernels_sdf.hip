@@ -42,15 +42,16 @@ void k_dmin_poly(const float4* __restrict__ poses, int npose,
     }
 }
 
-// Polygons of more than 16 padded vertices: a lane pair per pose, each lane
-// holding half the edges (PolyHalf), the even lane merges the pose's key.
-template <int HB, bool MOVING, bool ARGMIN>
+// Polygons of more than 16 padded vertices: a group of L lanes per pose (a
+// pair up to 32 vertices, a quad above), each lane holding HB edges
+// (PolyPart); the group's first lane merges the pose's key.
+template <int HB, int L, bool MOVING, bool ARGMIN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-void k_dmin_poly_pair(const float4* __restrict__ poses, int npose, PoseTime pt, PointArgs pts,
+void k_dmin_poly_part(const float4* __restrict__ poses, int npose, PoseTime pt, PointArgs pts,
                       int chunk, const float2* __restrict__ verts, unsigned int* __restrict__ key,
                       unsigned long long* __restrict__ key64) {
     extern __shared__ __align__(16) float lds[];  // point tiles: 8- and 16-byte LDS accesses
-    const int g = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 1);
+    const int g = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / L);
     const bool live = g < npose;
     const float4 q = live ? poses[g] : make_float4(0.f, 0.f, 1.f, 0.f);
     const float tau = MOVING ? pose_tau(pt, g) : 0.0f;
@@ -59,8 +60,8 @@ void k_dmin_poly_pair(const float4* __restrict__ poses, int npose, PoseTime pt, 
     const int c1 = min(c0 + chunk, nv);
     float best;
     int besti;
-    dmin_poly_pair_range<HB, MOVING, ARGMIN>(q, tau, pts, c0, c1, verts, lds, best, besti);
-    if (live && (threadIdx.x & 1) == 0) {
+    dmin_poly_part_range<HB, L, MOVING, ARGMIN>(q, tau, pts, c0, c1, verts, lds, best, besti);
+    if (live && (threadIdx.x & (L - 1)) == 0) {
         if (ARGMIN) {
             const unsigned int idx = besti >= 0 ? static_cast<unsigned int>(pts.idx[besti]) : 0xFFFFFFFFu;
             atomicMin(&key64[g], (static_cast<unsigned long long>(dkey(best)) << 32) | idx);
@@ -231,22 +232,29 @@ hipError_t launch_rect_t(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t
     return hipGetLastError();
 }
 
-template <int HB, bool MOVING, bool ARGMIN>
-hipError_t launch_pair_t(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_dmin_poly_pair<HB, MOVING, ARGMIN>), grid, dim3(L.block), lds, s, L.poses,
-                       L.npose, L.pt, L.pts, L.chunk, L.verts, L.key, L.key64);
+template <int HB, int L, bool MOVING, bool ARGMIN>
+hipError_t launch_part_t(const DminLaunch& D, dim3 grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_dmin_poly_part<HB, L, MOVING, ARGMIN>), grid, dim3(D.block), lds, s,
+                       D.poses, D.npose, D.pt, D.pts, D.chunk, D.verts, D.key, D.key64);
     return hipGetLastError();
+}
+
+template <int HB, int L>
+hipError_t launch_part(const DminLaunch& D, dim3 grid, size_t lds, hipStream_t s) {
+    // L lanes per pose
+    const dim3 gl((L * D.npose + D.block - 1) / D.block, grid.y);
+    if (D.pts.vx) return D.argmin ? launch_part_t<HB, L, true, true>(D, gl, lds, s)
+                                  : launch_part_t<HB, L, true, false>(D, gl, lds, s);
+    return D.argmin ? launch_part_t<HB, L, false, true>(D, gl, lds, s)
+                    : launch_part_t<HB, L, false, false>(D, gl, lds, s);
 }
 
 template <int P>
 hipError_t launch_poly(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s) {
-    if constexpr (P > 16) {
-        // two lanes per pose
-        const dim3 g2((2 * L.npose + L.block - 1) / L.block, grid.y);
-        if (L.pts.vx) return L.argmin ? launch_pair_t<P / 2, true, true>(L, g2, lds, s)
-                                      : launch_pair_t<P / 2, true, false>(L, g2, lds, s);
-        return L.argmin ? launch_pair_t<P / 2, false, true>(L, g2, lds, s)
-                        : launch_pair_t<P / 2, false, false>(L, g2, lds, s);
+    if constexpr (P > 32) {
+        return launch_part<P / 4, 4>(L, grid, lds, s);
+    } else if constexpr (P > 16) {
+        return launch_part<P / 2, 2>(L, grid, lds, s);
     } else {
         if (L.pts.vx) return L.argmin ? launch_poly_t<P, true, true>(L, grid, lds, s)
                                       : launch_poly_t<P, true, false>(L, grid, lds, s);
@@ -267,10 +275,14 @@ hipError_t launch_rect(const DminLaunch& L, dim3 grid, size_t lds, hipStream_t s
 
 int dmin_padded_count(int kind, int count) {
     // polygons: the exact count up to 16 vertices (one lane per pose), even
-    // counts above (a lane pair per pose, half the edges each); padding
-    // repeats vertex 0: zero-length edges that change neither the minimum
-    // nor the crossing parity
-    if (kind == 0) return count <= 16 ? (count < 3 ? 3 : count) : ((count + 1) / 2) * 2;
+    // counts up to 32 (a lane pair per pose, half the edges each), multiples
+    // of 4 above (a lane quad per pose); padding repeats vertex 0:
+    // zero-length edges that change neither the minimum nor the crossing
+    // parity
+    if (kind == 0) {
+        if (count <= 16) return count < 3 ? 3 : count;
+        return count <= 32 ? ((count + 1) / 2) * 2 : ((count + 3) / 4) * 4;
+    }
     static const int rb[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int b : rb)
         if (count <= b) return b;
@@ -288,7 +300,8 @@ hipError_t launch_dmin(const DminLaunch& L, hipStream_t s) {
             EMPPI_CASE(9) EMPPI_CASE(10) EMPPI_CASE(11) EMPPI_CASE(12) EMPPI_CASE(13)
             EMPPI_CASE(14) EMPPI_CASE(15) EMPPI_CASE(16) EMPPI_CASE(18) EMPPI_CASE(20)
             EMPPI_CASE(22) EMPPI_CASE(24) EMPPI_CASE(26) EMPPI_CASE(28) EMPPI_CASE(30)
-            EMPPI_CASE(32)
+            EMPPI_CASE(32) EMPPI_CASE(36) EMPPI_CASE(40) EMPPI_CASE(44) EMPPI_CASE(48)
+            EMPPI_CASE(52) EMPPI_CASE(56) EMPPI_CASE(60) EMPPI_CASE(64)
 #undef EMPPI_CASE
         default: return hipErrorInvalidValue;
         }

@@ -171,15 +171,16 @@ struct PolyFrame {
     }
 };
 
-// Half of a footprint of 2 HB (padded) vertices for a pair of lanes that
-// share one pose: the lane of parity h holds edges [h HB, (h + 1) HB), rotated
-// exactly as in PolyFrame, and the y of the vertex closing its last edge.
-// Halving the per-lane registers lets large polygons run at the occupancy of
-// small ones; the pair's partial minima and crossing parities are combined
-// per point (min and parity are exact, so the result is the same bits as
-// one lane holding every edge).
-template <int HB>
-struct PolyHalf {
+// Part of a footprint of L HB (padded) vertices for L = 2 or 4 consecutive
+// lanes that share one pose: lane j of the group holds edges
+// [j HB, (j + 1) HB), rotated exactly as in PolyFrame, and the y of the
+// vertex closing its last edge.  Splitting the per-lane registers lets large
+// polygons run at the occupancy of small ones; the group's partial minima
+// and crossing parities are combined per point (min and parity are exact, so
+// the result is the same bits as one lane holding every edge).
+template <int HB, int L>
+struct PolyPart {
+    static_assert(L == 2 || L == 4, "lane groups of 2 or 4");
     float X[HB], Y[HB], EX[HB], EY[HB], SX[HB], SY[HB], SL[HB];
     float Yend;
 
@@ -190,7 +191,7 @@ struct PolyHalf {
             X[b] = __builtin_fmaf(c, v.x, -(s * v.y));
             Y[b] = __builtin_fmaf(s, v.x, c * v.y);
         }
-        const float2 vn = verts[(b0 + HB) % (2 * HB)];
+        const float2 vn = verts[(b0 + HB) % (L * HB)];
         const float Xn = __builtin_fmaf(c, vn.x, -(s * vn.y));
         const float Yn = __builtin_fmaf(s, vn.x, c * vn.y);
 #pragma unroll
@@ -232,19 +233,25 @@ struct PolyHalf {
     }
 };
 
-// Signed squared distance from a lane pair's partial results (lanes 2k,
-// 2k + 1): the smaller minimum, negative when exactly one half saw an odd
-// number of crossings.  The parities combine on the scalar unit (the wave's
-// parity mask XOR the same mask with the bits of each pair swapped); the
-// minima are non-negative, so their integer order is their float order and
-// the partner's value arrives through a DPP quad permutation [1, 0, 3, 2]
-// folded into the integer min.  Every lane of the wave must be active.
-__device__ __forceinline__ float pair_combine(float m, unsigned long long odd) {
-    const unsigned long long partner =
-        ((odd >> 1) & 0x5555555555555555ull) | ((odd << 1) & 0xAAAAAAAAAAAAAAAAull);
-    const bool neg = __builtin_amdgcn_inverse_ballot_w64(odd ^ partner);
-    const int mi = __float_as_int(m);
-    const float mm = __int_as_float(min(mi, __builtin_amdgcn_mov_dpp(mi, 0xB1, 0xF, 0xF, true)));
+// Signed squared distance from a lane group's partial results (lanes
+// L k .. L k + L - 1): the smallest minimum, negative when the group saw an
+// odd number of crossings in total.  The parities combine on the scalar
+// unit (the wave's parity mask XOR the same mask with the bits of each pair
+// swapped; for quads, that result XOR itself with the pairs of each quad
+// swapped); the minima are non-negative, so their integer order is their
+// float order and the partners' values arrive through DPP quad
+// permutations ([1, 0, 3, 2], then [2, 3, 0, 1] for quads) folded into
+// integer mins.  Every lane of the wave must be active.
+template <int L>
+__device__ __forceinline__ float part_combine(float m, unsigned long long odd) {
+    unsigned long long par =
+        odd ^ (((odd >> 1) & 0x5555555555555555ull) | ((odd << 1) & 0xAAAAAAAAAAAAAAAAull));
+    if (L == 4) par ^= ((par >> 2) & 0x3333333333333333ull) | ((par << 2) & 0xCCCCCCCCCCCCCCCCull);
+    const bool neg = __builtin_amdgcn_inverse_ballot_w64(par);
+    int mi = __float_as_int(m);
+    mi = min(mi, __builtin_amdgcn_mov_dpp(mi, 0xB1, 0xF, 0xF, true));
+    if (L == 4) mi = min(mi, __builtin_amdgcn_mov_dpp(mi, 0x4E, 0xF, 0xF, true));
+    const float mm = __int_as_float(mi);
     return neg ? -mm : mm;
 }
 
@@ -286,15 +293,15 @@ __device__ __forceinline__ void dmin_poly_range(float4 q, float tau, const Point
     }
 }
 
-// Same with a lane pair per pose (2 HB padded vertices, see PolyHalf); both
-// lanes of a pair return the pose's minimum.  Every lane of the workgroup
-// must call it with the same range.
-template <int HB, bool MOVING, bool ARGMIN = false>
-__device__ __forceinline__ void dmin_poly_pair_range(float4 q, float tau, const PointArgs& pts,
+// Same with a group of L lanes per pose (L HB padded vertices, see
+// PolyPart); every lane of a group returns the pose's minimum.  Every lane
+// of the workgroup must call it with the same range.
+template <int HB, int L, bool MOVING, bool ARGMIN = false>
+__device__ __forceinline__ void dmin_poly_part_range(float4 q, float tau, const PointArgs& pts,
                                                      int c0, int c1, const float2* __restrict__ verts,
                                                      float* lds, float& best, int& besti) {
-    PolyHalf<HB> F;
-    F.init(verts, (threadIdx.x & 1) * HB, q.z, q.w);
+    PolyPart<HB, L> F;
+    F.init(verts, (threadIdx.x & (L - 1)) * HB, q.z, q.w);
     best = INFINITY;
     besti = -1;
     for (int t0 = c0; t0 < c1; t0 += DMIN_TILE) {
@@ -310,15 +317,15 @@ __device__ __forceinline__ void dmin_poly_pair_range(float4 q, float tau, const 
             point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
             F.eval(dx0, dy0, m0, o0);
             F.eval(dx1, dy1, m1, o1);
-            take<ARGMIN>(pair_combine(m0, o0), t0 + i, best, besti);
-            take<ARGMIN>(pair_combine(m1, o1), t0 + i + 1, best, besti);
+            take<ARGMIN>(part_combine<L>(m0, o0), t0 + i, best, besti);
+            take<ARGMIN>(part_combine<L>(m1, o1), t0 + i + 1, best, besti);
         }
         if (i < tn) {
             float dx, dy, m;
             unsigned long long o;
             point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
             F.eval(dx, dy, m, o);
-            take<ARGMIN>(pair_combine(m, o), t0 + i, best, besti);
+            take<ARGMIN>(part_combine<L>(m, o), t0 + i, best, besti);
         }
     }
 }

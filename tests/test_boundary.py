@@ -102,13 +102,15 @@ def test_check_polygon(poly, code):
 def test_check_polygon_capacity_and_scene_shapes():
     pkg, _ = _lib()
     from paper_2605_29663_amd import scenes
-    a = np.linspace(0, 2 * np.pi, 34)[:-1]
+    a = np.linspace(0, 2 * np.pi, 66)[:-1]                  # 65 vertices: above the capacity
     assert pkg.check_footprint(pkg.POLYGON, np.stack([np.cos(a), np.sin(a)], 1))[0] == -4
+    a = np.linspace(0, 2 * np.pi, 65)[:-1]                  # 64 vertices: the capacity
+    assert pkg.check_footprint(pkg.POLYGON, np.stack([np.cos(a), np.sin(a)], 1))[0] == 0
     for V in [scenes.FOOTPRINT_L8, scenes.FOOTPRINT_TOWED16, scenes.RECTS_4_BOUNDARY,
               scenes.FOOTPRINT_GAP_L] + [scenes.SHAPES_LTF[k][0] for k in "LTF"]:
         assert pkg.check_footprint(pkg.POLYGON, V)[0] == 0
     rng = np.random.default_rng(0)
-    for B in range(3, 33):
+    for B in range(3, 65):
         assert pkg.check_footprint(pkg.POLYGON, scenes.star_polygon(rng, B))[0] == 0
 
 

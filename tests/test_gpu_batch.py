@@ -20,8 +20,8 @@ def pkg():
 
 
 def _mixed_scenes():
-    """Twelve small scenes covering every register class of the persistent
-    kernel (small, medium and lane-pair polygons, odd and even vertex counts,
+    """Fourteen small scenes covering every register class of the persistent
+    kernel (small, medium, lane-pair and lane-quad polygons, odd and even vertex counts,
     static and moving points, small and large rectangle covers), all motion
     models and a scene without validation."""
     out = []
@@ -68,6 +68,12 @@ def _mixed_scenes():
     p12 = scenes.params("c1", K=64, T=5, goal=(1.5, 1.5))          # lane pairs, 30 padded
     out.append((p12, dict(ox=pts[:400, 0].copy(), oy=pts[:400, 1].copy(),
                           polygon=scenes.star_polygon(rng, 29), rects=None)))
+    p13 = scenes.params("c3", K=68, T=5, footprint_kind=0, goal=(-1.5, -1.0))  # quads, 48 padded
+    s13 = {k: (v[:500] if isinstance(v, np.ndarray) and v.ndim == 1 else v) for k, v in s3.items()}
+    out.append((p13, dict(s13, polygon=scenes.star_polygon(rng, 45), rects=None)))
+    p14 = scenes.params("c1", K=64, T=6, goal=(2.0, 2.0))           # quads, 64 vertices
+    out.append((p14, dict(ox=pts[:450, 0].copy(), oy=pts[:450, 1].copy(),
+                          polygon=scenes.star_polygon(rng, 64), rects=None)))
     return out
 
 

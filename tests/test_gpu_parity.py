@@ -65,7 +65,8 @@ POLYS = {"L8": scenes.FOOTPRINT_L8, "towed16": scenes.FOOTPRINT_TOWED16,
          "union20": scenes.RECTS_4_BOUNDARY, "gapL": scenes.FOOTPRINT_GAP_L,
          "tri": np.array([(0.0, 0.0), (1.0, 0.1), (0.3, 0.9)]),
          "star32": scenes.star_polygon(np.random.default_rng(32), 32),
-         "star5": scenes.star_polygon(np.random.default_rng(5), 5)}
+         "star5": scenes.star_polygon(np.random.default_rng(5), 5),
+         "star64": scenes.star_polygon(np.random.default_rng(64), 64)}
 
 
 @pytest.mark.parametrize("name", sorted(POLYS))
@@ -119,7 +120,10 @@ def _random_poses(rng, K, T, spread=2.0):
 FUSED_POLYS = {"towed16": scenes.FOOTPRINT_TOWED16,
                "star7": scenes.star_polygon(np.random.default_rng(7), 7),
                "star13": scenes.star_polygon(np.random.default_rng(13), 13),
-               "star27": scenes.star_polygon(np.random.default_rng(27), 27)}
+               "star27": scenes.star_polygon(np.random.default_rng(27), 27),
+               "star33": scenes.star_polygon(np.random.default_rng(33), 33),
+               "star50": scenes.star_polygon(np.random.default_rng(50), 50),
+               "star64": scenes.star_polygon(np.random.default_rng(64), 64)}
 
 
 @pytest.mark.parametrize("kind,moving,masked,poly", [(0, False, False, "towed16"),
@@ -128,10 +132,15 @@ FUSED_POLYS = {"towed16": scenes.FOOTPRINT_TOWED16,
                                                      (0, False, False, "star27"),
                                                      (0, False, True, "star7"),
                                                      (0, True, False, "star13"),
+                                                     (0, True, True, "star33"),
+                                                     (0, False, True, "star50"),
+                                                     (0, False, False, "star64"),
+                                                     (0, True, False, "star64"),
                                                      (1, False, True, None), (1, True, False, None)])
 def test_sdf_min_poses(ctx, pkg, orc, kind, moving, masked, poly):
     """Polygons of odd vertex counts run unpadded (one lane per pose); the
-    27-vertex polygon is padded to 28 (a lane pair per pose)."""
+    27-vertex polygon is padded to 28 (a lane pair per pose); above 32
+    vertices a lane quad shares a pose (33 -> 36, 50 -> 52 padded, 64 exact)."""
     rng = np.random.default_rng(10 * kind + 2 * moving + masked + 100 * len(poly or ""))
     K, T, N, dt = 100, 7, 2500, 0.1            # 700 poses (ragged vs 64), 3 LDS tiles
     poses = _random_poses(rng, K, T)
@@ -175,10 +184,12 @@ def test_sdf_min_poses_empty_and_all_masked(ctx, pkg):
     assert np.all(np.isposinf(_np(d))) and np.all(_np(am) == -1)
 
 
-def test_sdf_min_poses_large_n_ragged(ctx, pkg, orc):
-    """Many chunks and LDS tiles: N = 30001 points, 130 poses, polygon B = 32."""
+@pytest.mark.parametrize("poly", ["star32", "star64"])
+def test_sdf_min_poses_large_n_ragged(ctx, pkg, orc, poly):
+    """Many chunks and LDS tiles: N = 30001 points, 130 poses, polygon B = 32
+    (lane pairs) and B = 64 (lane quads)."""
     rng = np.random.default_rng(7)
-    V = POLYS["star32"]
+    V = POLYS[poly]
     poses = _random_poses(rng, 13, 10, spread=5.0)
     N = 30001
     ox, oy = rng.uniform(-8, 8, N).astype(np.float32), rng.uniform(-8, 8, N).astype(np.float32)
@@ -299,6 +310,23 @@ def test_step_parity_small(ctx, pkg, orc, name, K, N, T):
     _check_step_rows(orc, prm, sc, q0, U0, 0x5EED, 3, u_star, valid, D, Ut)
 
 
+@pytest.mark.parametrize("B", [37, 64])
+def test_step_parity_large_polygon(ctx, pkg, orc, B):
+    """Whole step with a footprint of 37 (padded to 40) and 64 vertices: the
+    distance stage runs a lane quad per pose, the validation pass too."""
+    import torch
+    prm, sc = _step_case("c2", 160, 1300, 18)
+    sc = dict(sc, polygon=scenes.star_polygon(np.random.default_rng(B), B, 0.15, 0.4))
+    _load_scene(ctx, pkg, prm, sc)
+    rng = np.random.default_rng(B + 1)
+    U0 = (0.3 * rng.standard_normal((prm["T"], prm["nu"]))).astype(np.float32)
+    U0 = np.clip(U0, np.float32(prm["u_min"]), np.float32(prm["u_max"]))
+    q0 = np.float32([0.02, 0.01, -0.03])
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=0xB16, step=5, diag=True)
+    _check_step_rows(orc, prm, sc, q0, U0, 0xB16, 5, u_star, valid, D, Ut)
+
+
 @pytest.mark.parametrize("name,path", [("c2", [(0.0, 0.0), (2.0, 0.3), (2.0, 0.3), (4.0, -1.0)]),
                                        ("c1", [(1.0, 0.5)])])
 def test_step_parity_with_guidance(ctx, pkg, orc, name, path):
@@ -416,10 +444,15 @@ def test_step_deterministic(ctx, pkg):
         assert np.array_equal(o[3], outs[0][3])
 
 
-def test_step_bitwise_identical_across_tiles(ctx, pkg):
-    """Every tile shape (and the autotuner's pick) gives bit-identical outputs."""
+@pytest.mark.parametrize("poly", [None, "star64"])
+def test_step_bitwise_identical_across_tiles(ctx, pkg, poly):
+    """Every tile shape (and the autotuner's pick) gives bit-identical outputs,
+    with the 16-vertex footprint (one lane per pose) and a 64-vertex one (a
+    lane quad per pose)."""
     import torch
     prm, sc = _step_case("c2", K=256, N=2000, T=16)
+    if poly:
+        sc = dict(sc, polygon=0.4 * POLYS[poly])
     _load_scene(ctx, pkg, prm, sc)
     ref = None
     shapes = [(0, 0), (64, 1), (64, 7), (128, 3), (256, 2), (256, 31)]
