@@ -136,7 +136,8 @@ FUSED_POLYS = {"towed16": scenes.FOOTPRINT_TOWED16,
                                                      (0, False, True, "star50"),
                                                      (0, False, False, "star64"),
                                                      (0, True, False, "star64"),
-                                                     (1, False, True, None), (1, True, False, None)])
+                                                     (1, False, True, None), (1, True, False, None),
+                                                     (1, True, True, "r32")])
 def test_sdf_min_poses(ctx, pkg, orc, kind, moving, masked, poly):
     """Polygons of odd vertex counts run unpadded (one lane per pose); the
     27-vertex polygon is padded to 28 (a lane pair per pose); above 32
@@ -149,7 +150,7 @@ def test_sdf_min_poses(ctx, pkg, orc, kind, moving, masked, poly):
     if moving:
         vx, vy = rng.uniform(-1, 1, N).astype(np.float32), rng.uniform(-1, 1, N).astype(np.float32)
     valid = (rng.uniform(size=N) < 0.6).astype(np.uint8) if masked else None
-    geom = FUSED_POLYS[poly] if kind == 0 else scenes.RECTS_4
+    geom = FUSED_POLYS[poly] if kind == 0 else RECTS[poly] if poly else scenes.RECTS_4
     ctx.set_footprint(kind, geom)
     ctx.set_points(ox, oy, vx, vy, valid)
     d, am = ctx.sdf_min_poses(poses, dt=dt, state_offset=1, kind=kind, argmin=True)
@@ -310,6 +311,38 @@ def test_step_parity_small(ctx, pkg, orc, name, K, N, T):
     _check_step_rows(orc, prm, sc, q0, U0, 0x5EED, 3, u_star, valid, D, Ut)
 
 
+def test_step_parity_max_horizon(ctx, pkg, orc):
+    """The longest horizon (T = 128): the rollout kernel's 8 chunks of 16
+    steps, the update over 128 steps and the 128-pose validation pass, every
+    row against the oracle."""
+    import torch
+    prm, sc = _step_case("c2", 128, 1200, 128)
+    _load_scene(ctx, pkg, prm, sc)
+    rng = np.random.default_rng(128)
+    U0 = (0.2 * rng.standard_normal((prm["T"], prm["nu"]))).astype(np.float32)
+    U0 = np.clip(U0, np.float32(prm["u_min"]), np.float32(prm["u_max"]))
+    q0 = np.float32([0.0, 0.01, 0.0])
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=0x7128, step=2, diag=True)
+    _check_step_rows(orc, prm, sc, q0, U0, 0x7128, 2, u_star, valid, D, Ut)
+
+
+def test_step_parity_max_rollouts(ctx, pkg, orc):
+    """The largest K (2^20 rollouts) with a short horizon: noise, rollouts,
+    costs, weights, update and validation of every rollout against the
+    oracle, d_min on 4096 sampled poses."""
+    import torch
+    prm, sc = _step_case("c1", 1 << 20, None, 4)
+    _load_scene(ctx, pkg, prm, sc)
+    K, T = prm["K"], prm["T"]
+    sample = np.sort(np.random.default_rng(20).choice(K * T, 4096, replace=False))
+    U0 = np.tile(np.float32([0.4, 0.1]), (T, 1))
+    q0 = np.zeros(3, np.float32)
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=0x20, step=1, diag=True)
+    _check_step_rows(orc, prm, sc, q0, U0, 0x20, 1, u_star, valid, D, Ut, sample=sample)
+
+
 @pytest.mark.parametrize("B", [37, 64])
 def test_step_parity_large_polygon(ctx, pkg, orc, B):
     """Whole step with a footprint of 37 (padded to 40) and 64 vertices: the
@@ -419,7 +452,7 @@ def test_step_errors(ctx, pkg):
         c2.mppi_step(prm, np.zeros(3), Ut, 1, 0)
     assert e.value.code == pkg.MPPI_E_NO_FOOTPRINT
     c2.set_footprint(pkg.POLYGON, scenes.FOOTPRINT_L8)
-    for bad in (dict(K=0), dict(T=129), dict(nu=3), dict(lambda_=0.0)):
+    for bad in (dict(K=0), dict(K=(1 << 20) + 1), dict(T=129), dict(nu=3), dict(lambda_=0.0)):
         with pytest.raises(pkg.MppiError):
             c2.mppi_step(dict(prm, **bad), np.zeros(3), Ut, 1, 0)
     with pytest.raises(pkg.MppiError) as e:
