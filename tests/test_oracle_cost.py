@@ -118,3 +118,21 @@ def test_path_following_term_hand_values(orc):
     g = scenes.params("c1", goal=(3.0, 4.0))
     assert abs(orc.phi_task(g, 0.0, 0.0) - 5.0) < 1e-6
     assert abs(orc.phi_task(dict(g, w_path=7.0), 0.0, 0.0) - 5.0) < 1e-6
+
+
+def test_step_independent_of_thread_count(orc):
+    """The oracle's parallel loops write disjoint outputs: one thread and all
+    threads give the same step bit for bit (the CPU baseline times both)."""
+    prm, sc = scenes.config("c1", K=96, T=8)
+    U0 = np.zeros((prm["T"], 2), np.float32)
+    n = orc.num_threads()
+    try:
+        orc.set_num_threads(1)
+        assert orc.num_threads() == 1
+        one = orc.mppi_step(prm, np.zeros(3, np.float32), U0, sc, 5, 2)
+    finally:
+        orc.set_num_threads(n)
+    assert orc.num_threads() == n
+    many = orc.mppi_step(prm, np.zeros(3, np.float32), U0, sc, 5, 2)
+    for k in ("d", "Jt", "U_upd", "u_star", "valid"):
+        np.testing.assert_array_equal(np.asarray(one[k]), np.asarray(many[k]))
