@@ -34,9 +34,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # 256 CUs x 128 lanes/clock x 2.4 GHz.
 VALU_PEAK_TOPS = 157.3 / 2
 
-# Minimal VALU lane-instructions per unit of work (derivation in the design doc):
-#   polygon: 12 per (pose, point, edge) + 4 per (pose, point)
-#   rectangle cover: 10 per (pose, point, box) + 7 per (pose, point)
+# Minimal VALU lane-instructions per unit of work, counted by hand from the
+# formulas (not read back from the compiled code):
+#   polygon, 12 per (pose, point, edge): w = p - v (2 sub), the clamped
+#     projection (mul + fma, clamp as an output modifier), r = w - t e (2 fma),
+#     |r|^2 (mul + fma), running min, crossing test (3 compares / mul);
+#     4 per (pose, point): o - t (2), sign select, min over points
+#   rectangle cover, 10 per (pose, point, box): |p - c| - h (4), max, min,
+#     max0, squares (mul + fma), min; 7 per (pose, point): o - t (2),
+#     rotation into the body frame (4), min
 OPS = {0: (12.0, 4.0), 1: (10.0, 7.0)}
 
 
@@ -421,8 +427,8 @@ def run_batched(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md and not implemented",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding across "
+                                   "GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_probe_mib:
