@@ -27,10 +27,13 @@ def _ctx(pkg, sc, kind=0):
     return c
 
 
-@pytest.mark.parametrize("name", ["c1", "c3"])
+@pytest.mark.parametrize("name", ["c1", "c3", "c1-quad"])
 def test_graph_mode_equals_eager(pkg, name):
+    """c1-quad: the c1 scene with a 64-vertex footprint (lane quads)."""
     import torch
-    prm, sc = scenes.config(name, K=256 if name == "c3" else 256, T=20)
+    prm, sc = scenes.config(name.split("-")[0], K=256, T=20)
+    if name.endswith("quad"):
+        sc = dict(sc, polygon=scenes.star_polygon(np.random.default_rng(64), 64, 0.15, 0.4))
     kind = prm["footprint_kind"]
     eager, graph = _ctx(pkg, sc, kind), _ctx(pkg, sc, kind)
     graph.mppi_set_graph(True)

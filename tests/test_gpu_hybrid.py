@@ -91,8 +91,13 @@ def pkgmodel(p):
     return orc.MODELS[p["model"]] if isinstance(p["model"], str) else p["model"]
 
 
-def test_hybrid_cycle_matches_oracle(pkg, orc):
+@pytest.mark.parametrize("B", [None, 64])
+def test_hybrid_cycle_matches_oracle(pkg, orc, B):
+    """The Ranger-like 6-vertex footprint, and a 64-vertex one (the lane-quad
+    register class of the batched distance pass)."""
     sc = _scene()
+    if B:
+        sc["polygon"] = scenes.star_polygon(np.random.default_rng(B), B, 0.15, 0.4)
     modes = _modes(goal=tuple(float(g) for g in sc["goal"]))
     rng = np.random.default_rng(2)
     U0s = [np.clip(0.3 * rng.standard_normal((24, p["nu"])), p["u_min"], p["u_max"]).astype(np.float32)
