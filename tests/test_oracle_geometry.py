@@ -61,7 +61,7 @@ def _regular(B, R=1.0, rot=0.3, c=(0.2, -0.1)):
     return np.stack([c[0] + R * np.cos(a), c[1] + R * np.sin(a)], axis=1)
 
 
-@pytest.mark.parametrize("B", [3, 4, 5, 7, 16])
+@pytest.mark.parametrize("B", [3, 4, 5, 7, 16, 33, 64])
 def test_convex_polygon_support_form(orc, B):
     """Inside a convex polygon d = max_b n_b.(p - v_b); at the centre d = -R cos(pi/B)."""
     V = _regular(B)
@@ -161,7 +161,7 @@ def test_distance_vs_dense_boundary_samples(orc, poly):
 def test_raycast_and_winding_agree(orc):
     rng = np.random.default_rng(3)
     for _ in range(30):
-        V = scenes.star_polygon(rng, int(rng.integers(3, 33)))
+        V = scenes.star_polygon(rng, int(rng.integers(3, 65)))
         for p in rng.uniform(-1.5, 1.5, size=(200, 2)):
             assert (orc.winding(V, *p) != 0) == bool(orc.inside_raycast(V, *p))
 
@@ -188,7 +188,7 @@ def test_shapes_are_simple_and_covers_match(orc):
 # ---------------------------------------------------------------- invariants
 
 def _poly_strategy():
-    return st.tuples(st.integers(3, 24), st.integers(0, 2**31 - 1))
+    return st.tuples(st.integers(3, 64), st.integers(0, 2**31 - 1))
 
 
 @settings(max_examples=40, deadline=None)
