@@ -44,9 +44,12 @@ void k_dmin_poly(const float4* __restrict__ poses, int npose,
 
 // Polygons of more than 16 padded vertices: a group of L lanes per pose (a
 // pair up to 32 vertices, a quad above), each lane holding HB edges
-// (PolyPart); the group's first lane merges the pose's key.
+// (PolyPart); the group's first lane merges the pose's key.  Register
+// budget: 4 waves per SIMD for static points (at 16 edges per lane the
+// compiler then spills only in the set-up, not in the point loop), 3 for
+// moving points (whose point loop would spill at 4).
 template <int HB, int L, bool MOVING, bool ARGMIN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MOVING ? 3 : 4)))
 void k_dmin_poly_part(const float4* __restrict__ poses, int npose, PoseTime pt, PointArgs pts,
                       int chunk, const float2* __restrict__ verts, unsigned int* __restrict__ key,
                       unsigned long long* __restrict__ key64) {
