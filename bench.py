@@ -3,9 +3,13 @@
 
 A step is one pass of Algorithm 1 (sampling, rollouts, rollout-frame
 transform, exact polygon signed distance, masked min over points, costs,
-softmax update, nominal re-rollout and validation) on the Ackermann corridor
-workload: K = 2048 rollouts, T = 40 steps, N = 8192 obstacle points, 16-vertex
-non-convex footprint, FP32 on the GPU.
+softmax update, nominal re-rollout and validation).  The default workload is
+the largest single-GPU one: 64 independent scenes of uneven size (K 512..4096
+rollouts, T 20..60 steps, N 1e3..3e4 points, 4..32-vertex star-shaped
+footprints, unicycle / Ackermann) in one batched step replayed from a
+captured hipGraph.  --config c1 | c2 | c3 run the single-scene workloads
+(unicycle open field, Ackermann corridor, omni rectangle cover with moving
+points).  FP32 on the GPU.
 
 Prints ONE JSON line.  `value` is SDF evaluations per second of the whole step
 (point-edge pairs of the sampled rollouts plus the validation pass, divided by
@@ -13,8 +17,9 @@ the step's wall time); `ms_per_step` is the step latency.  `roofline` reports
 the dominant kernel (fused transform + signed distance + min) against the
 VALU issue peak, timed with HIP events recorded on the library's stream
 around every launch of that kernel in the timed region.  `cpu_baseline` is the
-CPU oracle timed on a bounded sample of the same step, on all host threads
-(`value`, `cores`) and on one thread (`one_thread`), with the host CPU model.
+CPU oracle timed on a bounded sample of the same workload, on all host
+threads (`value`, `cores`) and on one thread (`one_thread`), with the host
+CPU model.
 """
 from __future__ import annotations
 
@@ -34,16 +39,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # 256 CUs x 128 lanes/clock x 2.4 GHz.
 VALU_PEAK_TOPS = 157.3 / 2
 
-# Minimal VALU lane-instructions per unit of work, counted by hand from the
-# formulas (not read back from the compiled code):
-#   polygon, 12 per (pose, point, edge): w = p - v (2 sub), the clamped
-#     projection (mul + fma, clamp as an output modifier), r = w - t e (2 fma),
-#     |r|^2 (mul + fma), running min, crossing test (3 compares / mul);
-#     4 per (pose, point): o - t (2), sign select, min over points
-#   rectangle cover, 10 per (pose, point, box): |p - c| - h (4), max, min,
-#     max0, squares (mul + fma), min; 7 per (pose, point): o - t (2),
-#     rotation into the body frame (4), min
-OPS = {0: (12.0, 4.0), 1: (10.0, 7.0)}
+# Algorithmic VALU lane-instructions per unit of work, counted by hand from
+# the formulas (not read back from the compiled code).  `frac` uses the
+# count that assumes packed FP32 pairs (a 2-vector add or fma counts once):
+#   11 per (pose, point, primitive): polygon edge w = p - v (1 packed add),
+#     w . e' (mul + fma), clamp (med3), r = w - t e (1 packed fma), |r|^2
+#     (mul + fma), running min, crossing test (2 compares + 1 fma); box
+#     |p - c| - h (1 packed add, 2 abs-sub), max, min, 2 max0, squares (mul +
+#     fma), signed square (fma), min;
+#   5 per (pose, point): transform 3, sign select 1, min over points 1, and
+#     1 more for a moving point (o + v t).
+# The library is built with packed FP32 disabled, so 2-vector adds and fmas
+# issue as two instructions; the same formulas then need
+#   12 per polygon edge and 4 per (pose, point) (the clamp is an output
+#     modifier of the fma, the parity XOR runs on the scalar unit), and
+#   10 per box and 7 per (pose, point) for the rectangle cover,
+# reported as `frac_unpacked_count` beside `frac`.
+OPS = {0: (11.0, 5.0), 1: (11.0, 5.0)}
+OPS_MOVING_EXTRA = 1.0
+OPS_UNPACKED = {0: (12.0, 4.0), 1: (10.0, 7.0)}
+
+
+def roofline_ops(kind, pairs, pose_points, moving=False, unpacked=False):
+    """VALU lane-instructions of one launch of the distance pass."""
+    per_unit, per_pose_point = (OPS_UNPACKED if unpacked else OPS)[kind]
+    if moving and not unpacked:
+        per_pose_point += OPS_MOVING_EXTRA
+    return pairs * per_unit + pose_points * per_pose_point
 
 
 def parse():
@@ -51,16 +73,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2",
+    ap.add_argument("--config", default="c4",
                     choices=["c1", "c2", "c3", "c4", "hybrid", "cloud", "exp1", "proposal"],
-                    help="c1/c2/c3: single-scene step; c4: 64-scene batched step (graph); "
+                    help="c4 (default): 64-scene batched step (graph); c1/c2/c3: single-scene step; "
                          "hybrid: three-mode cycle (Algorithm 2); cloud: point-cloud downsampling; "
                          "exp1: point-wise polygon vs rectangle-cover evaluator (L, T, F shapes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the tile shapes instead of using the shipped table")
     ap.add_argument("--cpu-reps", type=int, default=4,
-                    help="whole oracle steps timed for the CPU baseline")
+                    help="whole oracle steps timed for the CPU baseline (c1..c3); scenes of "
+                         "the batch timed for it (c4, twice this many)")
     ap.add_argument("--graph", action="store_true",
                     help="time steps replayed from a captured graph of a one-scene batch "
                          "(autotuned persistent distance kernel, timed on as many eager steps "
@@ -395,10 +418,12 @@ def run_batched(args):
     Bs = np.array([len(sc["polygon"]) for _, sc in cases], np.float64)
     pairs_main = float(np.sum(Ks * Ts * Ns * Bs))
     pairs_step = pairs_main + float(np.sum(Ts * Ns * Bs))
-    per_unit, per_pose_point = OPS[0]
-    ops = pairs_main * per_unit + float(np.sum(Ks * Ts * Ns)) * per_pose_point
+    pose_points = float(np.sum(Ks * Ts * Ns))
+    ops = roofline_ops(0, pairs_main, pose_points)
+    ops_unpacked = roofline_ops(0, pairs_main, pose_points, unpacked=True)
     k_avg = k_ms / max(k_n, 1)
     achieved = ops / (k_avg / 1e3) / 1e12
+    achieved_unpacked = ops_unpacked / (k_avg / 1e3) / 1e12
     items_main, items_val, _ = b.mppi_batch_info()
     out = {
         "metric": "SDF evals/s (K*T*N*edges per MPPI step) and MPPI step latency",
@@ -415,13 +440,60 @@ def run_batched(args):
         "roofline": {"bound": "alu", "kernel": "k_dmin_persistent (sampled-rollout pass)",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "count": "11 per point-edge pair + 5 per pose-point pair",
+                     "frac_unpacked_count": achieved_unpacked / VALU_PEAK_TOPS,
                      "traffic": traffic_record("c4"), "kernel_ms": k_avg, "launches": k_n,
                      "timing": "HIP events around the persistent launches of eager steps",
                      "tiles": {"pairs_per_item": work, "items_main": items_main,
                                "items_validation": items_val, "source": "batch autotuner"}},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(cases, pairs_step, max(1, 2 * args.cpu_reps))
     print(json.dumps(out))
     b.close()
+
+
+def cpu_baseline_batched(cases, pairs_step, n_sample):
+    """The oracle's whole step on the n_sample scenes of median size (by
+    point-edge pairs) on all host threads, scaled to the batch by pair count;
+    one scene at K = 64 on one thread."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as orc
+
+    def pairs(prm, sc):
+        return (prm["K"] * prm["T"] + prm["T"]) * sc["ox"].size * len(sc["polygon"])
+
+    order = sorted(range(len(cases)), key=lambda s: pairs(*cases[s]))
+    mid = len(order) // 2
+    pick = sorted(order[max(0, mid - n_sample // 2):max(0, mid - n_sample // 2) + n_sample])
+    ts = time.perf_counter()
+    done = 0
+    for s in pick:
+        prm, sc = cases[s]
+        orc.mppi_step(prm, np.zeros(3, np.float32), np.zeros((prm["T"], prm["nu"]), np.float32),
+                      sc, 1000 + s, 0)
+        done += pairs(prm, sc)
+    cpu_s = time.perf_counter() - ts
+    n_threads = orc.num_threads()
+    prm, sc = cases[order[mid]]
+    prm1 = dict(prm, K=64)
+    orc.set_num_threads(1)
+    ts = time.perf_counter()
+    orc.mppi_step(prm1, np.zeros(3, np.float32), np.zeros((prm["T"], prm["nu"]), np.float32), sc,
+                  1, 0)
+    one_s = time.perf_counter() - ts
+    orc.set_num_threads(n_threads)
+    return {"value": done / cpu_s, "unit": "evals/s",
+            "ms_per_step": cpu_s * 1e3 * pairs_step / done,
+            "cores": n_threads, "kind": "oracle",
+            "sample": f"whole oracle steps of the {len(pick)} scenes of median size "
+                      f"(scenes {pick}, {done:.3g} of the batch's {pairs_step:.3g} point-edge "
+                      f"pairs), {cpu_s:.1f} s; ms_per_step scaled to the whole batch by pair count",
+            "one_thread": {"value": pairs(prm1, sc) / one_s, "unit": "evals/s",
+                           "sample": f"one whole oracle step of scene {order[mid]} with K=64, "
+                                     f"{one_s:.1f} s"},
+            "host_cpu": host_cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -517,10 +589,12 @@ def main():
     pairs_main = K * T * N * P
     pairs_step = pairs_main + (T * N * P if prm["validate"] else 0)
     value = pairs_step / (ms_step / 1e3)
-    per_unit, per_pose_point = OPS[kind]
-    ops_launch = pairs_main * per_unit + K * T * N * per_pose_point
+    moving = sc.get("ovx") is not None
+    ops_launch = roofline_ops(kind, pairs_main, K * T * N, moving)
+    ops_unpacked = roofline_ops(kind, pairs_main, K * T * N, moving, unpacked=True)
     k_avg_ms = k_ms / max(k_n, 1)
     achieved = ops_launch / (k_avg_ms / 1e3) / 1e12
+    achieved_unpacked = ops_unpacked / (k_avg_ms / 1e3) / 1e12
     workload = args.config
 
     out = {
@@ -550,6 +624,9 @@ def main():
                                 "k_dmin_poly" if P <= 16 else "k_dmin_poly_part"),
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "count": f"11 per point-{'edge' if kind == 0 else 'box'} pair + "
+                              f"{5 + (1 if moving else 0)} per pose-point pair",
+                     "frac_unpacked_count": achieved_unpacked / VALU_PEAK_TOPS,
                      "traffic": (None if args.graph or args.polygon_vertices else
                                  traffic_record(workload)),
                      "kernel_ms": k_avg_ms, "launches": k_n,

@@ -380,6 +380,16 @@ MPPI_API int mppi_batch_info(mppi_batch b, long long* items_main, long long* ite
 /* J_nom (see mppi_diag) of every scene from the last batched step: host n. */
 MPPI_API int mppi_batch_nominal_costs(mppi_batch b, float* J_out);
 
+/* Diagnostics of scene `scene` from the last batched (or hybrid) step, read
+ * from the batch's workspaces into device buffers of `diag` (the layouts of
+ * mppi_diag): d_min (decoded from the merged distance keys exactly as the
+ * cost stage decodes them), poses, eps, J, U_upd, d_nom (NaN where
+ * validation is off) and J_nom; each may be NULL.  argmin, w and u are not
+ * kept by a batch and must be NULL (MPPI_E_ARG).  The workspaces hold the
+ * last step until the next step, refresh, set_work or autotune of the batch
+ * (MPPI_E_STATE when no step ran since the last plan).  Synchronous.       */
+MPPI_API int mppi_batch_scene_diag(mppi_batch b, int scene, const mppi_diag* diag);
+
 /* Timing of the sampled-rollout signed-distance pass (all persistent
  * launches of one step, HIP events on the batch's stream) over the eager
  * steps (use_graph = 0) run since profiling was enabled; graph replays are

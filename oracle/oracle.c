@@ -314,13 +314,16 @@ EXPORT void orc_update(int K, int T, int nu, const double* w, const double* eps,
 }
 
 /* Validation and execution (Algorithm 1 step 4): the nominal is valid when
- * every d_h^{min,nom} >= d_safe.  Valid: u* = U_0 and U is shifted forward
- * (the last entry is repeated).  Invalid: u* = 0 and U is reset to zero.
- * Returns 1 when valid.                                                     */
+ * every d_h^{min,nom} >= d_safe.  A nominal with a non-finite control has no
+ * defined trajectory (its states, hence its distances, are not numbers), so
+ * it is never valid.  Valid: u* = U_0 and U is shifted forward (the last
+ * entry is repeated).  Invalid: u* = 0 and U is reset to zero.  Returns 1
+ * when valid.                                                               */
 EXPORT int orc_validate_shift(int T, int nu, const double* dnom, double d_safe,
                               double* U, double* u_star) {
     int ok = 1;
     for (int h = 0; h < T; ++h) if (!(dnom[h] >= d_safe)) ok = 0;
+    for (int k = 0; k < T * nu; ++k) if (!isfinite(U[k])) ok = 0;
     if (ok) {
         for (int c = 0; c < nu; ++c) u_star[c] = U[c];
         for (int h = 0; h + 1 < T; ++h)

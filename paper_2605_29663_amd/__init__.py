@@ -32,7 +32,7 @@ EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footpri
            "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
            "mppi_batch_u_offsets", "mppi_batch_refresh", "mppi_step_batched",
            "mppi_batch_autotune", "mppi_batch_set_work", "mppi_batch_info", "mppi_batch_nominal_costs",
-           "mppi_batch_set_profiling", "mppi_batch_get_profile",
+           "mppi_batch_set_profiling", "mppi_batch_get_profile", "mppi_batch_scene_diag",
            "mppi_hybrid_create", "mppi_hybrid_destroy", "mppi_hybrid_last_error",
            "mppi_hybrid_batch", "mppi_hybrid_step",
            "proposal_create", "proposal_destroy", "proposal_last_error", "proposal_num_params",
@@ -138,6 +138,7 @@ def load():
     L.mppi_batch_set_profiling.argtypes = [vp, i]
     L.mppi_batch_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_longlong)]
+    L.mppi_batch_scene_diag.argtypes = [vp, i, ctypes.POINTER(MppiDiag)]
     L.mppi_hybrid_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(MppiParams), i, vp]
     L.mppi_hybrid_destroy.argtypes = [vp]
     L.mppi_hybrid_last_error.argtypes = [vp]
@@ -407,6 +408,17 @@ class Context:
         return np.array(u_out[:nu], dtype=np.float32), bool(valid.value), out
 
 
+def _scene_diag(lib, h, p, s, device, check):
+    K, T, nu = p.K, p.T, p.nu
+    out = dict(d_min=torch.empty((K, T), device=device), poses=torch.empty((K, T, 4), device=device),
+               eps=torch.empty((K, T, nu), device=device), J=torch.empty(K, device=device),
+               U_upd=torch.empty((T, nu), device=device), d_nom=torch.empty(T, device=device),
+               J_nom=torch.empty(1, device=device))
+    D = MppiDiag(*[out[k].data_ptr() if k in out else None for k in MppiDiag.names()])
+    check(lib.mppi_batch_scene_diag(h, int(s), ctypes.byref(D)))
+    return out
+
+
 class Batch:
     """Batched step over several contexts (one scene each).
 
@@ -501,6 +513,12 @@ class Batch:
         self._check(self.lib.mppi_batch_get_profile(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def scene_diag(self, s):
+        """Diagnostics of scene s from the last step (see mppi_batch_scene_diag):
+        dict of device tensors d_min (K, T), poses (K, T, 4), eps (K, T, nu),
+        J (K,), U_upd (T, nu), d_nom (T,), J_nom (1,)."""
+        return _scene_diag(self.lib, self.h, self.params[s], s, self.device, self._check)
+
     def nominal_costs(self):
         """J_nom of every scene from the last step (NaN where validation is off)."""
         J = np.zeros(self.n, dtype=np.float32)
@@ -559,6 +577,12 @@ class Hybrid:
     def nominal(self, U, m):
         p = self.params[m]
         return U[self.u_offsets[m]:self.u_offsets[m + 1]].view(p.T, p.nu)
+
+    def mode_diag(self, m):
+        """Diagnostics of mode m's Algorithm-1 cycle from the last hybrid step
+        (the layout of Batch.scene_diag)."""
+        return _scene_diag(self.lib, self.lib.mppi_hybrid_batch(self.h), self.params[m], m,
+                           self.device, self._check)
 
     def step(self, q0, U, seed, step, hp, m_prev, tau_cool, use_graph=True):
         """One cycle.  hp: dict of mppi_hybrid_params fields.  U: packed per-mode

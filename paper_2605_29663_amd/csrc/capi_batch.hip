@@ -35,6 +35,7 @@ struct mppi_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool planned = false;
+    bool stepped = false;           // a step ran since the workspaces were carved
     bool capturing = false;
     // HIP-event timing of the sampled-rollout signed-distance pass (eager steps)
     bool prof = false, prof_pending = false;
@@ -276,6 +277,7 @@ int plan(mppi_batch b, double work_target) {
         }
     snapshot(b);
     b->planned = true;
+    b->stepped = false;
     return MPPI_OK;
 }
 
@@ -495,6 +497,7 @@ int mppi_step_batched(mppi_batch b, const float* q0, float* dU, const uint64_t* 
     if (int rc = batch_launch(b, q0, dU, seeds, steps, use_graph)) return rc;
     BHIP(b, hipStreamSynchronize(b->stream));
     batch_collect(b, u_out, valid_out);
+    b->stepped = true;
     return MPPI_OK;
 }
 
@@ -522,6 +525,20 @@ int mppi_batch_get_profile(mppi_batch b, double* ms, long long* launches) {
 int mppi_batch_nominal_costs(mppi_batch b, float* J_out) {
     if (!b || !J_out) return MPPI_E_ARG;
     for (int s = 0; s < b->n; ++s) J_out[s] = b->h_out[OUT_FLOATS * s + 4];
+    return MPPI_OK;
+}
+
+int mppi_batch_scene_diag(mppi_batch b, int scene, const mppi_diag* diag) {
+    if (!b) return MPPI_E_ARG;
+    if (!diag || scene < 0 || scene >= b->n) return bfail(b, MPPI_E_ARG, "need a diag and 0 <= scene < %d", b->n);
+    if (diag->argmin || diag->w || diag->u)
+        return bfail(b, MPPI_E_ARG, "the batch keeps no argmin, weights or sampled controls");
+    if (!b->stepped) return bfail(b, MPPI_E_STATE, "no batched step since the last plan");
+    DeviceGuard g(b->device);
+    const mppi_params& P = b->prms[scene];
+    const SceneDiag d{diag->d_min, diag->poses, diag->eps, diag->J, diag->U_upd, diag->d_nom, diag->J_nom};
+    BHIP(b, launch_scene_diag(b->bufs[scene], P.K, b->args[scene].Kpad, P.T, P.nu, d, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
     return MPPI_OK;
 }
 
@@ -702,6 +719,7 @@ int mppi_hybrid_step(mppi_hybrid h, const float q0[3], float* dU, uint64_t seed,
                            b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     batch_collect(b, nullptr, nullptr);
+    b->stepped = true;
     for (int k = 0; k < 3; ++k) u_out[k] = h->h_res[k];
     *m_prev = static_cast<int>(h->h_res[3]);
     *tau_cool = static_cast<int>(h->h_res[4]);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -42,7 +43,19 @@ struct DevBuf {
         const size_t want = std::max<size_t>(bytes, 256);
         hipError_t e = hipMalloc(&p, want);
         if (e == hipSuccess) cap = want;
+        // EXACT_MPPI_POISON=1 fills every new workspace with 0xFF bytes (NaN
+        // as float, the largest key as an integer), so that a kernel reading
+        // a workspace entry no kernel wrote shows up in the results instead
+        // of depending on what the allocator hands back
+        if (e == hipSuccess && poison()) {
+            e = hipMemset(p, 0xFF, want);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+        }
         return e;
+    }
+    static bool poison() {
+        const char* v = std::getenv("EXACT_MPPI_POISON");
+        return v && v[0] && v[0] != '0';
     }
     void release() {
         if (p) (void)hipFree(p);

@@ -57,6 +57,11 @@ __device__ __forceinline__ unsigned int dkey(float s) {
 __device__ __forceinline__ float dkey_value(unsigned int k) {
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
+// Signed distance sign(s) sqrt|s| of a merged key (one square root per pose).
+__device__ __forceinline__ float dkey_distance(unsigned int k) {
+    const float sq = dkey_value(k);
+    return sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
+}
 
 // One launch of the fused transform + signed distance + min-over-points
 // stage: npose poses, points split into nchunk chunks of `chunk` points;
@@ -188,6 +193,15 @@ hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs,
                                   hipStream_t s);
 hipError_t launch_finalize_batched(const SceneStep* steps, const SceneBufs* bufs, int n,
                                    hipStream_t s);
+// Diagnostics of one scene of the last batched step in the caller's [r][h]
+// layouts (any output may be nullptr): d_min decoded from the merged keys,
+// scored poses, clipped perturbations, J~, the updated nominal, d_nom
+// (validation pass) and J_nom.
+struct SceneDiag {
+    float *d_min, *poses, *eps, *J, *U_upd, *d_nom, *J_nom;
+};
+hipError_t launch_scene_diag(const SceneBufs& B, int K, int Kpad, int T, int nu,
+                             const SceneDiag& d, hipStream_t s);
 // Workgroups of k_dmin_persistent<cls> (block threads) resident per compute
 // unit on the current device, from the occupancy calculator (registers and
 // the LDS tile); 0 on error.

@@ -215,6 +215,32 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_b(const SceneStep* __r
                    sh);
 }
 
+// Diagnostics of one scene from its workspace: thread g < K*T handles pose
+// (r, h) = (g / T, g % T); the first K, T*nu and T threads also copy J~, the
+// updated nominal and the validation distances.
+__global__ void k_scene_diag(SceneBufs B, int K, int Kpad, int T, int nu, SceneDiag d) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < K * T) {
+        const int r = g / T, h = g - r * T;
+        const int src = h * Kpad + r;
+        if (d.d_min) d.d_min[g] = dkey_distance(B.key[src]);
+        if (d.poses) {
+            const float4 q = B.poses[src];
+            d.poses[4 * static_cast<size_t>(g)] = q.x;
+            d.poses[4 * static_cast<size_t>(g) + 1] = q.y;
+            d.poses[4 * static_cast<size_t>(g) + 2] = q.z;
+            d.poses[4 * static_cast<size_t>(g) + 3] = q.w;
+        }
+        if (d.eps)
+            for (int c = 0; c < nu; ++c)
+                d.eps[static_cast<size_t>(g) * nu + c] = B.eps_ws[(h * nu + c) * Kpad + r];
+    }
+    if (d.J && g < K) d.J[g] = B.jt[g];
+    if (d.U_upd && g < T * nu) d.U_upd[g] = B.unew[g];
+    if (d.d_nom && g < T) d.d_nom[g] = B.validate ? dkey_distance(B.key_nom[g]) : NAN;
+    if (d.J_nom && g == 0) d.J_nom[0] = B.out[4];
+}
+
 // Hybrid-mode selection (Algorithm 2 steps 2-3), one thread: penalised costs
 // Jbar_m = J_m + lambda_switch [m != m_prev] for validated modes (else
 // +inf); safe stop (zero command, previous mode) when no mode validated;
@@ -333,6 +359,14 @@ hipError_t launch_nominal_batched(const SceneStep* steps, const SceneBufs* bufs,
                                   hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_nominal_b, dim3(n), dim3(NOM_THREADS), 0, s, steps, bufs);
+    return hipGetLastError();
+}
+
+hipError_t launch_scene_diag(const SceneBufs& B, int K, int Kpad, int T, int nu,
+                             const SceneDiag& d, hipStream_t s) {
+    const long long n = std::max(static_cast<long long>(K) * T, 3ll * T);
+    const int blocks = static_cast<int>((n + 255) / 256);
+    hipLaunchKernelGGL(k_scene_diag, dim3(blocks), dim3(256), 0, s, B, K, Kpad, T, nu, d);
     return hipGetLastError();
 }
 

@@ -146,6 +146,11 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
                     if (o.diag_eps) o.diag_eps[d] = e;
                     if (o.diag_u) o.diag_u[d] = v;
                 }
+            } else if (o.eps_ws) {
+                // padding rollouts [K, Kpad): weight exp(-inf) = 0 in the
+                // update, which multiplies these entries, so they must hold a
+                // finite value (0 * NaN left over in reused memory is NaN)
+                for (int k = 0; k < nu; ++k) o.eps_ws[(h * nu + k) * Kpad + r] = 0.0f;
             }
             for (int k = 0; k < 3; ++k) su[(hh * 3 + k) * WAVE + lane] = u[k];
             sw[hh * WAVE + lane] = heading_rate(P.model, u, P.wheelbase);
@@ -220,16 +225,15 @@ __device__ __forceinline__ void cost_block(const StepArgs& P, const unsigned int
     if (r < P.K) {
         for (int h = grp; h < P.T; h += ngrp) {
             const size_t g = static_cast<size_t>(h) * P.Kpad + r;
-            float sq;
+            float d;
             int idx = -1;
             if (key64) {
                 const unsigned long long k = key64[g];
-                sq = dkey_value(static_cast<unsigned int>(k >> 32));
+                d = dkey_distance(static_cast<unsigned int>(k >> 32));
                 idx = static_cast<int>(static_cast<unsigned int>(k));
             } else {
-                sq = dkey_value(key[g]);
+                d = dkey_distance(key[g]);
             }
-            const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
             const float gap = fmaxf(P.d_safe - d, 0.0f);
             J += (d < 0.0f ? P.w_coll : 0.0f) + P.w_rep * (gap * gap);
             chi |= (d < P.d_safe) ? 1 : 0;
@@ -358,8 +362,8 @@ __device__ __forceinline__ void nominal_block(const StepArgs& P, const float* __
 }
 
 // Validation and execution (Algorithm 1 step 4): valid iff every
-// d_nom >= d_safe; then u* = U_0 and U shifts left (last entry repeated),
-// else u* = 0 and U = 0.  The noise-free cost of the updated nominal, J_nom =
+// d_nom >= d_safe and every control of the nominal is finite; then u* = U_0
+// and U shifts left (last entry repeated), else u* = 0 and U = 0.  The noise-free cost of the updated nominal, J_nom =
 // sum_h [phi_task + phi_ctrl + phi_obs] along the validation rollout (+ w_inf
 // if unsafe), is what the hybrid-mode selection compares across modes.
 // out = (u*_0, u*_1, u*_2, valid, J_nom, 0, 0, 0).  One thread per horizon
@@ -376,12 +380,14 @@ __device__ __forceinline__ void finalize_block(const StepArgs& P, int validate,
     int bad = 0;
     float term = 0.0f;
     if (validate && h < T) {
-        const float sq = dkey_value(key_nom[h]);
-        const float d = sq < 0.0f ? -__builtin_sqrtf(-sq) : __builtin_sqrtf(sq);
+        const float d = dkey_distance(key_nom[h]);
         bad = !(d >= P.d_safe);
         if (diag_dnom) diag_dnom[h] = d;
         float u[3] = {0.f, 0.f, 0.f};
         for (int k = 0; k < nu; ++k) u[k] = Unew[h * nu + k];
+        // a non-finite control has no defined trajectory: never valid (its
+        // poses are NaN, and NaN distances never lower the running minimum)
+        for (int k = 0; k < nu; ++k) bad |= !__builtin_isfinite(u[k]);
         const float4 p = nom[h];
         const float gap = fmaxf(P.d_safe - d, 0.0f);
         term = task_ctrl(P, p.x, p.y, u) + ((d < 0.0f ? P.w_coll : 0.0f) + P.w_rep * (gap * gap));

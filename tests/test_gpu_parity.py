@@ -11,11 +11,9 @@ import numpy as np
 import pytest
 
 from paper_2605_29663_amd import scenes
+from rowcheck import SIGN_BAND, TOL_D, assert_sdf_close, check_step_rows as _check_step_rows
 
 pytestmark = pytest.mark.gpu
-
-TOL_D = 1e-5
-SIGN_BAND = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -37,17 +35,6 @@ def ctx(pkg):
 
 def _np(t):
     return t.detach().cpu().numpy()
-
-
-def assert_sdf_close(d_gpu, d_orc, tol=TOL_D, band=SIGN_BAND):
-    d_gpu = np.asarray(d_gpu, dtype=np.float64)
-    fin = np.isfinite(d_orc)
-    assert np.array_equal(np.isfinite(d_gpu), fin)
-    assert np.all(d_gpu[~fin] == d_orc[~fin])
-    err = np.abs(d_gpu[fin] - d_orc[fin])
-    assert err.max(initial=0.0) <= tol, f"max |d err| {err.max()}"
-    far = fin & (np.abs(d_orc) >= band)
-    assert np.array_equal(np.signbit(d_gpu[far]), np.signbit(d_orc[far]))
 
 
 # ------------------------------------------------------------- point-wise SDF
@@ -245,62 +232,19 @@ def _load_scene(ctx, pkg, prm, sc):
     ctx.set_points(sc["ox"], sc["oy"], sc.get("ovx"), sc.get("ovy"), sc.get("valid"))
 
 
-def _check_step_rows(orc, prm, sc, q0, U0, seed, step, u_star, valid, D, U_after, sample=None):
-    """Row-by-row parity of one step from the GPU's own intermediates."""
-    K, T, nu = prm["K"], prm["T"], prm["nu"]
-    kind, geom = (0, sc["polygon"]) if prm["footprint_kind"] == 0 else (1, sc["rects"])
-    # a1, a2: noise and rollouts bit-exact
-    p_o, e_o, u_o = orc.rollout_f32(prm, q0, U0, seed, step)
-    poses, eps, us = _np(D["poses"]), _np(D["eps"]), _np(D["u"])
-    np.testing.assert_array_equal(eps, e_o)
-    np.testing.assert_array_equal(us, u_o)
-    np.testing.assert_array_equal(poses, p_o)
-    # a3-a6: d_min on the GPU's poses (all, or a sample at full size)
-    d = _np(D["d_min"]).astype(np.float64)
-    tau = orc.tau_of(prm, T, K)
-    flat = np.arange(K * T) if sample is None else sample
-    d_o = orc.dmin(poses.reshape(-1, 4)[flat], tau.ravel()[flat], sc["ox"], sc["oy"],
-                   sc.get("ovx"), sc.get("ovy"), sc.get("valid"), kind, geom)
-    assert_sdf_close(d.ravel()[flat], d_o)
-    # a7: J~ from the GPU's d_min, poses and controls
-    J, chi, Jt = orc.costs(prm, poses[..., :2], us, d)
-    Jg = _np(D["J"]).astype(np.float64)
-    np.testing.assert_allclose(Jg, Jt, rtol=1e-5)
-    # a8, a9: weights and update from the GPU's J~
-    w_o = orc.weights(Jg, prm["lambda_"])
-    np.testing.assert_allclose(_np(D["w"]), w_o, atol=1e-6, rtol=1e-5)
-    U_upd_o = orc.update(U0, w_o, eps)
-    U_upd = _np(D["U_upd"])
-    np.testing.assert_allclose(U_upd, U_upd_o, atol=1e-5)
-    # a10: nominal re-rollout of the GPU's update, validation, shift / reset
-    if prm.get("validate", 1):
-        nom = orc.rollout_nominal_f32(prm, q0, U_upd)
-        dn_o = orc.dmin(nom, orc.tau_of(prm, T), sc["ox"], sc["oy"], sc.get("ovx"),
-                        sc.get("ovy"), sc.get("valid"), kind, geom)
-        dn = _np(D["d_nom"]).astype(np.float64)
-        assert_sdf_close(dn, dn_o)
-        near = np.abs(dn_o - np.float32(prm["d_safe"])) < TOL_D
-        # the decision on the GPU's own d_nom is reproduced exactly, and the
-        # oracle's d_nom gives the same decision unless a value sits at d_safe
-        ok_o, us_o, Un_o = orc.validate_shift(U_upd, dn, prm["d_safe"])
-        assert valid == ok_o
-        if not near.any():
-            assert valid == orc.validate_shift(U_upd, dn_o, prm["d_safe"])[0]
-        np.testing.assert_array_equal(u_star, np.float32(us_o))
-        np.testing.assert_array_equal(_np(U_after), np.float32(Un_o))
-        # noise-free cost of the updated nominal, from the GPU's nominal and d_nom
-        Jn_o = orc.costs(prm, nom[None, :, :2], U_upd[None], dn[None])[2][0]
-        np.testing.assert_allclose(float(_np(D["J_nom"])[0]), Jn_o, rtol=1e-5, atol=1e-5)
-    else:
-        assert np.isnan(_np(D["J_nom"])[0])
-    return Jt
-
-
-@pytest.mark.parametrize("name,K,N,T", [("c1", None, None, None), ("c2", 192, 1500, None),
-                                        ("c3", 128, 2100, 24)])
-def test_step_parity_small(ctx, pkg, orc, name, K, N, T):
+@pytest.mark.parametrize("name,K,N,T,offset", [("c1", None, None, None, 1),
+                                               ("c2", 192, 1500, None, 1),
+                                               ("c3", 128, 2100, 24, 1),
+                                               ("c2", 192, 1500, None, 0),
+                                               ("c3", 128, 2100, 24, 0)])
+def test_step_parity_small(ctx, pkg, orc, name, K, N, T, offset):
+    """Every row of one step against the oracle.  offset = 0 is the literal
+    reading of the paper's cost (the (r, h) term scores the pre-step state
+    q_h, moving points at time h dt), with static (c2) and moving (c3)
+    points; offset = 1 scores q_{h+1}."""
     import torch
     prm, sc = _step_case(name, K, N, T)
+    prm["state_offset"] = offset
     _load_scene(ctx, pkg, prm, sc)
     rng = np.random.default_rng(11)
     U0 = (0.3 * rng.standard_normal((prm["T"], prm["nu"]))).astype(np.float32)
@@ -309,6 +253,61 @@ def test_step_parity_small(ctx, pkg, orc, name, K, N, T):
     Ut = torch.tensor(U0, device="cuda")
     u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=0x5EED, step=3, diag=True)
     _check_step_rows(orc, prm, sc, q0, U0, 0x5EED, 3, u_star, valid, D, Ut)
+
+
+def test_step_padding_rollouts_ignore_stale_workspace(ctx, pkg, orc, monkeypatch):
+    """K = 100 leaves rollouts [100, 128) as padding of the 64-wide layout.
+    Their weight is exp(-inf) = 0, so the update must not read whatever
+    their perturbation slots held: with every new workspace filled with NaN
+    bytes (EXACT_MPPI_POISON) the step still matches the oracle row by row,
+    for the single-scene step and for a batch of two scenes."""
+    import torch
+    monkeypatch.setenv("EXACT_MPPI_POISON", "1")
+    prm, sc = _step_case("c2", 100, 1500, 20)
+    c = pkg.Context(0)
+    try:
+        _load_scene(c, pkg, prm, sc)
+        rng = np.random.default_rng(100)
+        U0 = np.clip((0.3 * rng.standard_normal((prm["T"], prm["nu"]))).astype(np.float32),
+                     np.float32(prm["u_min"]), np.float32(prm["u_max"]))
+        q0 = np.float32([0.02, -0.01, 0.01])
+        Ut = torch.tensor(U0, device="cuda")
+        u_star, valid, D = c.mppi_step(prm, q0, Ut, seed=0x100, step=4, diag=True)
+        assert np.all(np.isfinite(_np(D["U_upd"])))
+        _check_step_rows(orc, prm, sc, q0, U0, 0x100, 4, u_star, valid, D, Ut)
+        prm2 = dict(prm, K=37, T=9)
+        b = pkg.Batch([c, c], [prm, prm2])
+        try:
+            U = b.new_nominals()
+            b.nominal(U, 0).copy_(torch.tensor(U0, device="cuda"))
+            u_b, v_b = b.mppi_step_batched(np.tile(q0, (2, 1)), U, [0x100, 0x100], [4, 4],
+                                           use_graph=False)
+            np.testing.assert_array_equal(u_b[0, :2], u_star)
+            np.testing.assert_array_equal(_np(b.nominal(U, 0)), _np(Ut))
+            for s in range(2):
+                assert np.all(np.isfinite(_np(b.scene_diag(s)["U_upd"])))
+        finally:
+            b.close()
+    finally:
+        c.close()
+
+
+def test_step_non_finite_nominal_holds(ctx, pkg, orc):
+    """A NaN in the nominal makes the updated nominal NaN there; its rollout
+    has NaN poses whose distances never lower the minimum (d_nom = +inf), so
+    only the finiteness rule stops it: hold (u* = 0) and reset, as in the
+    oracle, every row checked from the GPU's intermediates."""
+    import torch
+    prm, sc = _step_case("c2", 128, 1200, 16)
+    _load_scene(ctx, pkg, prm, sc)
+    U0 = np.zeros((prm["T"], prm["nu"]), np.float32)
+    U0[5, 0] = np.nan
+    q0 = np.zeros(3, np.float32)
+    Ut = torch.tensor(U0, device="cuda")
+    u_star, valid, D = ctx.mppi_step(prm, q0, Ut, seed=0xBAD, step=0, diag=True)
+    assert not valid and np.all(u_star == 0) and torch.all(Ut == 0)
+    assert np.isnan(_np(D["U_upd"])[5, 0]) and np.all(np.isposinf(_np(D["d_nom"])[5:]))
+    _check_step_rows(orc, prm, sc, q0, U0, 0xBAD, 0, u_star, valid, D, Ut)
 
 
 def test_step_parity_max_horizon(ctx, pkg, orc):
@@ -516,7 +515,8 @@ def test_step_bitwise_identical_across_tiles(ctx, pkg, poly):
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_step_full_size_sampled(ctx, pkg, orc, name):
     """Full-size configuration in the benchmark's launch shape; d_min checked on
-    a random sample of 256 (rollout, step) poses, everything else in full."""
+    a random 2 % of the (rollout, step) poses (1638 of 81920 at c2, 4096 of
+    204800 at c3), everything else in full."""
     import torch
     prm, sc = scenes.config(name)
     _load_scene(ctx, pkg, prm, sc)
@@ -524,7 +524,8 @@ def test_step_full_size_sampled(ctx, pkg, orc, name):
     q0 = np.zeros(3, np.float32)
     Ut = torch.tensor(U0, device="cuda")
     u_star, valid, D = ctx.mppi_step(prm, q0, Ut, 0x5EED0002, 0, diag=True)
-    sample = np.random.default_rng(0).choice(prm["K"] * prm["T"], 256, replace=False)
+    n_poses = prm["K"] * prm["T"]
+    sample = np.random.default_rng(0).choice(n_poses, n_poses // 50, replace=False)
     _check_step_rows(orc, prm, sc, q0, U0, 0x5EED0002, 0, u_star, valid, D, Ut, sample=sample)
 
 

@@ -70,6 +70,23 @@ def test_validate_shift(orc):
     assert not ok and list(us) == [0.0, 0.0] and np.all(Un == 0)
     ok, _, _ = orc.validate_shift(U, np.array([1.0, np.nan, 1.0, 1.0]), 0.05)
     assert not ok
+    # a non-finite control is never valid, even where every distance clears
+    # d_safe (a NaN nominal has NaN states; their distances are not numbers)
+    for bad in (np.nan, np.inf, -np.inf):
+        Ub = U.copy()
+        Ub[2, 1] = bad
+        ok, us, Un = orc.validate_shift(Ub, np.array([1.0, 1.0, 1.0, 1.0]), 0.05)
+        assert not ok and list(us) == [0.0, 0.0] and np.all(Un == 0)
+
+
+def test_nan_nominal_distances_never_lower_the_minimum(orc):
+    """Why the finiteness rule is needed: a NaN pose gives NaN point distances,
+    which a running minimum never takes, so d_min of a NaN nominal is +inf
+    and would clear d_safe by itself."""
+    nan_pose = np.array([[np.nan, np.nan, np.nan, np.nan]])
+    d = orc.dmin(nan_pose, None, np.float32([0.5, -1.0]), np.float32([0.2, 3.0]), kind=0,
+                 geom=scenes.FOOTPRINT_L8)
+    assert np.isposinf(d[0])
 
 
 def test_step_validation_forces_hold_and_reset(orc):
