@@ -236,6 +236,22 @@ MPPI_API int sdf_rectcover(mppi_ctx ctx, const float* dpx, const float* dpy, int
 MPPI_API int sdf_min_poses(mppi_ctx ctx, const float* dposes, int K, int T, float dt, int state_offset,
                   int kind, float* dd_min, int* dargmin);
 
+/* sdf_min_poses for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, arguments, layouts, stream ordering and results (bit
+ * for bit) as sdf_min_poses, but its distance keys live in a fixed device
+ * array of MPPI_NOALLOC_MAX_POSES entries that the library holds on every
+ * device it runs on until the process ends (set up by mppi_create), so the
+ * call allocates nothing; the caller still passes the poses and outputs.
+ * K * T above MPPI_NOALLOC_MAX_POSES: MPPI_E_CAPACITY; K = 0 does nothing
+ * (the output pointers may then be NULL).  Every call on one
+ * device shares that device's array: calls whose work overlaps on one device
+ * (two contexts on different streams, or two threads) race and corrupt each
+ * other's results; order them on one stream or synchronise between them.  */
+#define MPPI_NOALLOC_MAX_POSES (1 << 19)
+MPPI_API int sdf_min_poses_noalloc(mppi_ctx ctx, const float* dposes, int K, int T, float dt,
+                                   int state_offset, int kind, float* dd_min, int* dargmin);
+
 /* Noise-free augmented cost of n given control sequences from q0 (host, 3
  * floats): each sequence (device dUseq, n*T*nu floats, sequence-major) is
  * clamped to the control box, rolled out without noise and scored exactly as

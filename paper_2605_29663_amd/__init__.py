@@ -26,7 +26,8 @@ MODELS = {"unicycle": 0, "ackermann": 1, "omni": 2, "spin": 3, "parallel": 4}
 
 EXPORTS = ("mppi_create", "mppi_destroy", "mppi_last_error", "mppi_check_footprint",
            "set_footprint", "set_points", "set_guidance", "cloud_downsample",
-           "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "mppi_sequence_costs", "mppi_rollout", "mppi_step",
+           "sdf_polygon", "sdf_rectcover", "sdf_min_poses", "sdf_min_poses_noalloc",
+           "mppi_sequence_costs", "mppi_rollout", "mppi_step",
            "mppi_autotune", "mppi_tune_get", "mppi_tune_set", "mppi_set_tiles", "mppi_set_graph",
            "mppi_set_profiling", "mppi_get_profile",
            "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_last_error",
@@ -109,6 +110,7 @@ def load():
     L.sdf_polygon.argtypes = [vp, vp, vp, i, vp]
     L.sdf_rectcover.argtypes = [vp, vp, vp, i, vp]
     L.sdf_min_poses.argtypes = [vp, vp, i, i, f, i, i, vp, vp]
+    L.sdf_min_poses_noalloc.argtypes = [vp, vp, i, i, f, i, i, vp, vp]
     L.mppi_rollout.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp, vp, vp]
     L.mppi_sequence_costs.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, i, vp]
     L.mppi_step.argtypes = [vp, ctypes.POINTER(MppiParams), vp, vp, u64, u64, vp,
@@ -313,6 +315,21 @@ class Context:
         self._check(self.lib.sdf_min_poses(self.h, _ptr(poses), K, T, float(dt),
                                            int(state_offset), int(kind), _ptr(d), _ptr(am)))
         return (d, am) if argmin else d
+
+    def sdf_min_poses_noalloc(self, poses, d_min, argmin=None, dt=0.0, state_offset=1,
+                              kind=POLYGON):
+        """sdf_min_poses into caller-provided outputs with the library's fixed
+        workspace (no device allocation in the call).  poses (K, T, 4), d_min
+        (K, T) float32 and argmin (K, T) int32 or None: contiguous device tensors."""
+        for t, dt_ in ((poses, torch.float32), (d_min, torch.float32), (argmin, torch.int32)):
+            if t is not None and not (t.is_cuda and t.dtype == dt_ and t.is_contiguous()):
+                raise TypeError("poses, d_min, argmin: contiguous device tensors of the right type")
+        K, T = poses.shape[0], poses.shape[1]
+        if d_min.shape != (K, T) or (argmin is not None and argmin.shape != (K, T)):
+            raise ValueError("outputs must be (K, T)")
+        self._check(self.lib.sdf_min_poses_noalloc(self.h, _ptr(poses), K, T, float(dt),
+                                                   int(state_offset), int(kind), _ptr(d_min),
+                                                   _ptr(argmin)))
 
     def mppi_rollout(self, prm, q0, U, seed, step):
         p = make_params(prm)

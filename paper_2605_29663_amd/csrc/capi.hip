@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -22,6 +23,37 @@ using namespace emppi_host;
 
 static int rollout_into_ws(mppi_ctx ctx, const StepArgs& A, const float* dU, float* dposes,
                            float* deps, float* du, bool argmin, const float* useq = nullptr);
+
+// Fixed device workspace of sdf_min_poses_noalloc: the merged distance keys
+// of up to MPPI_NOALLOC_MAX_POSES poses (8 bytes each with the argmin, 4
+// without).  Every device the library runs on holds its own copy for the
+// life of the process.  In host code `scratch` names a host-side stand-in:
+// kernels get the device address looked up per device by mppi_create.
+static __device__ __align__(256) unsigned long long scratch[MPPI_NOALLOC_MAX_POSES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device `device`, looked up once.
+hipError_t scratch_lookup(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = p;
+    return e;
+}
+
+void* scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < SCRATCH_MAX_DEVICES ? g_scratch_ptr[device] : nullptr;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -42,6 +74,7 @@ int mppi_create(mppi_ctx* out, int device, void* hip_stream) {
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_out), OUT_FLOATS * sizeof(float), 0);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->n_valid.p, 0, sizeof(int), ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = scratch_lookup(device);  // the device is current (DeviceGuard)
     if (e != hipSuccess) {
         mppi_destroy(ctx);
         return fail(nullptr, MPPI_E_HIP, "context setup: %s", hipGetErrorString(e));
@@ -259,6 +292,34 @@ int sdf_min_poses(mppi_ctx ctx, const float* dposes, int K, int T, float dt, int
         HIP_TRY(ctx, ctx->key.ensure(sizeof(unsigned int) * np));
         key = ctx->key.as<unsigned int>();
     }
+    HIP_TRY(ctx, launch_key_init(key, key64, static_cast<int>(np), ctx->stream));
+    if (int rc = run_dmin(ctx, reinterpret_cast<const float4*>(dposes), static_cast<int>(np), pt, kind,
+                          key, key64))
+        return rc;
+    HIP_TRY(ctx, launch_dmin_finalize(key, key64, static_cast<int>(np), dd_min, dargmin, ctx->stream));
+    return MPPI_OK;
+}
+
+int sdf_min_poses_noalloc(mppi_ctx ctx, const float* dposes, int K, int T, float dt,
+                          int state_offset, int kind, float* dd_min, int* dargmin) {
+    if (!ctx) return MPPI_E_ARG;
+    if (K < 0 || T < 1 || (K > 0 && (!dposes || !dd_min))) return fail(ctx, MPPI_E_ARG, "bad arguments");
+    if (kind == MPPI_FP_POLYGON && !ctx->has_poly) return fail(ctx, MPPI_E_NO_FOOTPRINT, "no polygon footprint set");
+    if (kind == MPPI_FP_RECTS && !ctx->has_rect) return fail(ctx, MPPI_E_NO_FOOTPRINT, "no rectangle cover set");
+    if (kind != MPPI_FP_POLYGON && kind != MPPI_FP_RECTS) return fail(ctx, MPPI_E_ARG, "kind %d", kind);
+    const long long np = static_cast<long long>(K) * T;
+    if (np > MPPI_NOALLOC_MAX_POSES)
+        return fail(ctx, MPPI_E_CAPACITY, "K*T = %lld poses exceeds the fixed workspace of %d poses",
+                    np, MPPI_NOALLOC_MAX_POSES);
+    if (np == 0) return MPPI_OK;
+    void* ws = scratch_ptr(ctx->device);
+    if (!ws) return fail(ctx, MPPI_E_STATE, "fixed workspace not set up on device %d", ctx->device);
+    DeviceGuard g(ctx->device);
+    const PoseTime pt{1, T, state_offset ? 1 : 0, dt};
+    unsigned int* key = dargmin ? nullptr : static_cast<unsigned int*>(ws);
+    unsigned long long* key64 = dargmin ? static_cast<unsigned long long*>(ws) : nullptr;
+    // the keys start at their +inf value (a kernel, no memset): the array
+    // keeps whatever the previous call on this device left in it
     HIP_TRY(ctx, launch_key_init(key, key64, static_cast<int>(np), ctx->stream));
     if (int rc = run_dmin(ctx, reinterpret_cast<const float4*>(dposes), static_cast<int>(np), pt, kind,
                           key, key64))
