@@ -472,17 +472,32 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
         return rc;
     if (ctx->prof) HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIP_TRY(ctx, ctx->jt.ensure(sizeof(float) * Kpad));
-    HIP_TRY(ctx, launch_cost(A, key, key64, ctx->jbase.as<float>(), ctx->jt.as<float>(), D.d_min,
-                             D.argmin, ctx->stream));
+    HIP_TRY(ctx, ctx->unew.ensure(sizeof(float) * T * nu));
+    if (cost_update_fused(A.Kpad, A.T)) {
+        // 2-3. costs, weights and update in one launch (small K)
+        HIP_TRY(ctx, launch_cost_update(A, key, key64, ctx->jbase.as<float>(), ctx->eps_ws.as<float>(),
+                                        dU, ctx->unew.as<float>(), ctx->jt.as<float>(), D.w, D.d_min,
+                                        D.argmin, ctx->stream));
+    } else {
+        HIP_TRY(ctx, launch_cost(A, key, key64, ctx->jbase.as<float>(), ctx->jt.as<float>(), D.d_min,
+                                 D.argmin, ctx->stream));
+        // 3. weights and update
+        HIP_TRY(ctx, launch_update(A, ctx->jt.as<float>(), ctx->eps_ws.as<float>(), dU,
+                                   ctx->unew.as<float>(), D.w, ctx->stream));
+    }
     if (D.J)
         HIP_TRY(ctx, hipMemcpyAsync(D.J, ctx->jt.p, sizeof(float) * A.K, hipMemcpyDeviceToDevice, ctx->stream));
-    // 3. weights and update
-    HIP_TRY(ctx, ctx->unew.ensure(sizeof(float) * T * nu));
-    HIP_TRY(ctx, launch_update(A, ctx->jt.as<float>(), ctx->eps_ws.as<float>(), dU,
-                               ctx->unew.as<float>(), D.w, ctx->stream));
     // 4. validation
     HIP_TRY(ctx, ctx->key_nom.ensure(sizeof(unsigned int) * T));
-    if (prm->validate) {
+    const int padded = kind == MPPI_FP_POLYGON ? ctx->BP : ctx->RP;
+    if (prm->validate && validate_small_supported(kind, padded) &&
+        static_cast<long long>(T) * std::max(ctx->n_points, 0) * padded <= VAL_SMALL_MAX_PAIRS) {
+        // nominal, its distances and validation in one single-workgroup launch
+        HIP_TRY(ctx, launch_validate_small(A, kind, padded, point_args(ctx), ctx->poly_verts.as<float2>(),
+                                           ctx->rects.as<float4>(), ctx->unew.as<float>(), dU,
+                                           ctx->out.as<float>(), D.U_upd, D.d_nom, D.J_nom,
+                                           ctx->stream));
+    } else if (prm->validate) {
         HIP_TRY(ctx, ctx->nom_poses.ensure(sizeof(float4) * T));
         HIP_TRY(ctx, launch_nominal(A, ctx->unew.as<float>(), ctx->nom_poses.as<float4>(),
                                     ctx->key_nom.as<unsigned int>(), ctx->stream));
@@ -490,10 +505,14 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
         if (int rc = run_dmin(ctx, ctx->nom_poses.as<float4>(), A.T, ptn, kind,
                               ctx->key_nom.as<unsigned int>(), nullptr))
             return rc;
+        HIP_TRY(ctx, launch_finalize(A, 1, ctx->key_nom.as<unsigned int>(), ctx->nom_poses.as<float4>(),
+                                     ctx->unew.as<float>(), dU, ctx->out.as<float>(), D.U_upd, D.d_nom,
+                                     D.J_nom, ctx->stream));
+    } else {
+        HIP_TRY(ctx, launch_finalize(A, 0, ctx->key_nom.as<unsigned int>(), ctx->nom_poses.as<float4>(),
+                                     ctx->unew.as<float>(), dU, ctx->out.as<float>(), D.U_upd, D.d_nom,
+                                     D.J_nom, ctx->stream));
     }
-    HIP_TRY(ctx, launch_finalize(A, prm->validate ? 1 : 0, ctx->key_nom.as<unsigned int>(),
-                                 ctx->nom_poses.as<float4>(), ctx->unew.as<float>(), dU,
-                                 ctx->out.as<float>(), D.U_upd, D.d_nom, D.J_nom, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_out, ctx->out.p, OUT_FLOATS * sizeof(float), hipMemcpyDeviceToHost,
                                 ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -529,9 +548,12 @@ int mppi_autotune(mppi_ctx ctx, const mppi_params* prm, int reps, int* out_block
     const int blocks[] = {64, 128, 256};
     const int chunk_counts[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 13, 16, 20, 24, 32, 40, 48, 64, 96, 128};
     std::vector<std::pair<int, int>> cand;
+    // chunks of at least 32 points, 8 when there are few poses (the pass then
+    // needs the point chunks to fill the chip)
+    const int min_chunk = npose <= 16384 ? 8 : 32;
     for (int b : blocks)
         for (int nc : chunk_counts)
-            if (nc == 1 || ctx->n_points / nc >= 32) cand.emplace_back(b, nc);
+            if (nc == 1 || ctx->n_points / nc >= min_chunk) cand.emplace_back(b, nc);
     std::vector<float> best(cand.size(), 1e30f);
     unsigned int* key = ctx->key.as<unsigned int>();
     int rc = MPPI_OK;

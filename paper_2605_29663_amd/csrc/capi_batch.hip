@@ -37,6 +37,14 @@ struct mppi_batch_s {
     bool planned = false;
     bool stepped = false;           // a step ran since the workspaces were carved
     bool capturing = false;
+    // the register classes of a distance pass run concurrently: one on the
+    // batch's stream, the others on auxiliary streams (default priority)
+    // forked from and joined back into it, so a class's workgroups start as
+    // the previous class's drain and the pass has a single tail
+    static constexpr int NAUX = 3;
+    hipStream_t aux[NAUX] = {};
+    hipEvent_t ev_fork[2] = {}, ev_join[2][NAUX] = {};
+    std::vector<int> cls_order[2];  // classes with items, most work first
     // HIP-event timing of the sampled-rollout signed-distance pass (eager steps)
     bool prof = false, prof_pending = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -118,6 +126,7 @@ bool snapshot_matches(mppi_batch b) {
 // Build the work queue for a given target work per item, size and carve the
 // workspace arena, and upload the static tables.
 constexpr double DEFAULT_WORK_PER_ITEM = 4194304.0;
+constexpr int TAIL_SPLIT_MIN_POINTS = 32;  // tail items are split while parts keep this many points
 constexpr double MIN_WORK_PER_ITEM = 65536.0;
 
 // Plan for queue items of `work_target` point-primitive pairs (0: the
@@ -240,21 +249,53 @@ int plan(mppi_batch b, double work_target) {
             for (int g0 = 0; g0 < D.npose; g0 += tile) {
                 const int live = std::min(tile, D.npose - g0);
                 for (int k = 0; k < nck; ++k) {
-                    const int len = std::max(0, std::min(D.chunk, c->n_points - k * D.chunk));
+                    const int c0 = k * D.chunk;
+                    const int len = std::max(0, std::min(D.chunk, c->n_points - c0));
                     q[pass][cls].push_back({static_cast<double>(live) * (len + 8) * padded,
-                                            DminItem{pass * n + s, g0, k, 0}});
+                                            DminItem{pass * n + s, g0, c0, c0 + len}});
                 }
             }
         }
         for (int r0 = 0; r0 < Kpad; r0 += WAVE) b->blk_roll.push_back(make_int2(s, r0));
         for (int h = 0; h < T; ++h) b->blk_upd.push_back(make_int2(s, h));
     }
+    double class_work[2][DMIN_CLASSES] = {};
     for (int pass = 0; pass < 2; ++pass)
         for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
             auto& v = q[pass][cls];
             std::stable_sort(v.begin(), v.end(), [](const Cost& x, const Cost& y) { return x.c > y.c; });
-            for (auto& e : v) b->items[pass][cls].push_back(e.it);
+            // guided tail: the items of the last round of resident workgroups
+            // (the smallest, after the longest-first sort) are split in four
+            // along their point range, so the queue ends with quarter items
+            // and the workgroups finish within a quarter item of each other
+            double total = 0.0;
+            for (const auto& e : v) total += e.c;
+            const double round_work = v.empty() ? 0.0 : total / v.size() * b->resident[pass][cls];
+            size_t cut = v.size();
+            double suffix = 0.0;
+            while (cut > 0 && suffix + v[cut - 1].c <= round_work) suffix += v[--cut].c;
+            if (!v.empty()) class_work[pass][cls] = total;
+            for (size_t i = 0; i < v.size(); ++i) {
+                const DminItem it = v[i].it;
+                const int len = it.c1 - it.c0;
+                if (i < cut || len < 4 * TAIL_SPLIT_MIN_POINTS) {
+                    b->items[pass][cls].push_back(it);
+                    continue;
+                }
+                for (int part = 0; part < 4; ++part)
+                    b->items[pass][cls].push_back(DminItem{it.sd, it.g0, it.c0 + part * len / 4,
+                                                           it.c0 + (part + 1) * len / 4});
+            }
         }
+    for (int pass = 0; pass < 2; ++pass) {
+        auto& o = b->cls_order[pass];
+        o.clear();
+        for (int cls = 0; cls < DMIN_CLASSES; ++cls)
+            if (!b->items[pass][cls].empty()) o.push_back(cls);
+        std::stable_sort(o.begin(), o.end(), [&](int x, int y) {
+            return class_work[pass][x] > class_work[pass][y];
+        });
+    }
     // upload tables
     BHIP(b, hipStreamSynchronize(b->stream));
     BHIP(b, b->d_bufs.ensure(sizeof(SceneBufs) * n));
@@ -290,13 +331,27 @@ int persistent_grid(mppi_batch b, int pass, int cls, size_t n_items) {
 }
 
 int launch_dmin_pass(mppi_batch b, int pass) {
-    for (int cls = 0; cls < DMIN_CLASSES; ++cls) {
+    const std::vector<int>& order = b->cls_order[pass];
+    const int na = std::min(static_cast<int>(order.size()) - 1, mppi_batch_s::NAUX);
+    const bool fork = na > 0 && b->aux[0];
+    if (fork) {
+        BHIP(b, hipEventRecord(b->ev_fork[pass], b->stream));
+        for (int j = 0; j < na; ++j) BHIP(b, hipStreamWaitEvent(b->aux[j], b->ev_fork[pass], 0));
+    }
+    for (size_t i = 0; i < order.size(); ++i) {
+        const int cls = order[i];
         const auto& v = b->items[pass][cls];
-        if (v.empty()) continue;
+        hipStream_t s = (!fork || i == 0) ? b->stream : b->aux[(i - 1) % na];
         BHIP(b, launch_dmin_persistent(cls, persistent_block(pass), persistent_grid(b, pass, cls, v.size()),
                                        b->d_sdm.as<SceneDmin>(), b->d_items[pass][cls].as<DminItem>(),
                                        static_cast<int>(v.size()), b->d_counters.as<int>() + DMIN_CLASSES * pass + cls,
-                                       b->stream));
+                                       s));
+    }
+    if (fork) {
+        for (int j = 0; j < na; ++j) {
+            BHIP(b, hipEventRecord(b->ev_join[pass][j], b->aux[j]));
+            BHIP(b, hipStreamWaitEvent(b->stream, b->ev_join[pass][j], 0));
+        }
     }
     return MPPI_OK;
 }
@@ -428,6 +483,13 @@ int mppi_batch_create(mppi_batch* out, const mppi_ctx* scenes, const mppi_params
         e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         b->own_stream = e == hipSuccess;
     }
+    for (int j = 0; j < mppi_batch_s::NAUX && e == hipSuccess; ++j)
+        e = hipStreamCreateWithFlags(&b->aux[j], hipStreamNonBlocking);
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        e = hipEventCreateWithFlags(&b->ev_fork[pass], hipEventDisableTiming);
+        for (int j = 0; j < mppi_batch_s::NAUX && e == hipSuccess; ++j)
+            e = hipEventCreateWithFlags(&b->ev_join[pass][j], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = b->d_steps.ensure(sizeof(SceneStep) * n);
     if (e == hipSuccess) e = b->d_counters.ensure(sizeof(int) * 2 * DMIN_CLASSES);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_steps), sizeof(SceneStep) * n, 0);
@@ -461,6 +523,13 @@ int mppi_batch_destroy(mppi_batch b) {
         if (b->h_out) (void)hipHostFree(b->h_out);
         if (b->ev0) (void)hipEventDestroy(b->ev0);
         if (b->ev1) (void)hipEventDestroy(b->ev1);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (b->ev_fork[pass]) (void)hipEventDestroy(b->ev_fork[pass]);
+            for (hipEvent_t ev : b->ev_join[pass])
+                if (ev) (void)hipEventDestroy(ev);
+        }
+        for (hipStream_t st : b->aux)
+            if (st) (void)hipStreamDestroy(st);
         if (b->own_stream) (void)hipStreamDestroy(b->stream);
     }
     delete b;

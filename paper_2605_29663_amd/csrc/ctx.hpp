@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/exact_mppi.h"
+#include "host_geom.hpp"
 #include "kernels.hpp"
 
 using emppi::DminLaunch;
@@ -142,64 +143,10 @@ struct DeviceGuard {
     }
 };
 
-// Proper intersection or touching of segments ab and cd (double precision).
-inline double orient2(const double* a, const double* b, const double* c) {
-    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
-}
-inline bool on_segment(const double* a, const double* b, const double* p) {
-    return std::min(a[0], b[0]) <= p[0] && p[0] <= std::max(a[0], b[0]) &&
-           std::min(a[1], b[1]) <= p[1] && p[1] <= std::max(a[1], b[1]);
-}
-inline bool segments_meet(const double* a, const double* b, const double* c, const double* d) {
-    const double o1 = orient2(a, b, c), o2 = orient2(a, b, d);
-    const double o3 = orient2(c, d, a), o4 = orient2(c, d, b);
-    if (((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) && ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0)))
-        return true;
-    if (o1 == 0 && on_segment(a, b, c)) return true;
-    if (o2 == 0 && on_segment(a, b, d)) return true;
-    if (o3 == 0 && on_segment(c, d, a)) return true;
-    if (o4 == 0 && on_segment(c, d, b)) return true;
-    return false;
-}
-
-// Simple-polygon check: finite, no zero-length edge, non-zero area, and no
-// two non-adjacent edges meeting (adjacent edges may only share their common
-// vertex: a fold-back onto the previous edge is rejected too).
+// Simple-polygon check of set_footprint (host_geom.hpp holds the geometry).
 inline int check_polygon(mppi_ctx ctx, const std::vector<double>& v, int B) {
-    for (double x : v)
-        if (!std::isfinite(x)) return fail(ctx, MPPI_E_FOOTPRINT, "non-finite vertex coordinate");
-    double area2 = 0.0;
-    for (int b = 0; b < B; ++b) {
-        const double* p = &v[2 * b];
-        const double* q = &v[2 * ((b + 1) % B)];
-        if (p[0] == q[0] && p[1] == q[1])
-            return fail(ctx, MPPI_E_FOOTPRINT, "zero-length edge %d", b);
-        area2 += p[0] * q[1] - q[0] * p[1];
-    }
-    if (std::fabs(area2) * 0.5 < 1e-12) return fail(ctx, MPPI_E_FOOTPRINT, "polygon area below 1e-12");
-    for (int i = 0; i < B; ++i) {
-        const double* a = &v[2 * i];
-        const double* b = &v[2 * ((i + 1) % B)];
-        for (int j = i + 1; j < B; ++j) {
-            const double* c = &v[2 * j];
-            const double* d = &v[2 * ((j + 1) % B)];
-            const bool next = (j == i + 1), prev = ((j + 1) % B == i);
-            if (next || prev) {
-                // adjacent: collinear overlap beyond the shared vertex is a fold-back
-                const double* far = next ? d : c;          // the non-shared end of edge j
-                const double* far_i = next ? a : b;        // the non-shared end of edge i
-                const double* shared = next ? b : a;
-                if (orient2(a, b, far) == 0 && on_segment(a, b, far) &&
-                    !(far[0] == shared[0] && far[1] == shared[1]))
-                    return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d fold back", i, j);
-                if (orient2(c, d, far_i) == 0 && on_segment(c, d, far_i))
-                    return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d fold back", i, j);
-                continue;
-            }
-            if (segments_meet(a, b, c, d))
-                return fail(ctx, MPPI_E_FOOTPRINT, "edges %d and %d touch or cross (not simple)", i, j);
-        }
-    }
+    char msg[160];
+    if (polygon_defect(v, B, msg, sizeof msg)) return fail(ctx, MPPI_E_FOOTPRINT, "%s", msg);
     return MPPI_OK;
 }
 
@@ -302,7 +249,7 @@ inline void choose_tiles(int kind, int padded, int npose, int n_points, int& blo
     const int resident = 256 * 4 * dmin_waves_per_simd(kind, padded) / (block / WAVE);
     // a pass over few poses (the validation rollout) is bound by the serial
     // point loop of one wave: split the points finer
-    const int max_chunks = std::max(1, n_points / (pose_blocks == 1 ? 16 : 32));
+    const int max_chunks = std::max(1, n_points / (pose_blocks == 1 ? 16 : npose <= 16384 ? 8 : 32));
     int best_nc = 1;
     double best_eff = -1.0;
     for (int nc = 1; nc <= std::min(max_chunks, 4096); ++nc) {

@@ -124,6 +124,29 @@ hipError_t launch_finalize(const StepArgs& P, int validate, const unsigned int* 
                            const float4* nom, const float* Unew, float* U, float* out,
                            float* diag_unew, float* diag_dnom, float* diag_jnom, hipStream_t s);
 
+// Small steps (the single-scene path): cost + update in one launch when
+// cost_update_fused(Kpad, T), and nominal + validation distances +
+// validation in one single-workgroup launch when the footprint needs one lane
+// per pose (polygons of up to 16 vertices, rectangle covers) and T N
+// (padded primitives) <= VAL_SMALL_MAX_PAIRS.  Bit-identical to the separate
+// launches.
+constexpr int COST_UPDATE_MAX_KPAD = 512;               // LDS: 21 Kpad floats' worth
+constexpr long long COST_UPDATE_MAX_POSES = 1ll << 15;  // Kpad T: every workgroup decodes them all
+inline bool cost_update_fused(int Kpad, int T) {
+    return Kpad <= COST_UPDATE_MAX_KPAD && static_cast<long long>(Kpad) * T <= COST_UPDATE_MAX_POSES;
+}
+constexpr int VAL_SMALL_THREADS = 1024;
+constexpr long long VAL_SMALL_MAX_PAIRS = 1ll << 18;
+hipError_t launch_cost_update(const StepArgs& P, const unsigned int* key,
+                              const unsigned long long* key64, const float* jbase,
+                              const float* eps_ws, const float* U, float* Unew, float* jt,
+                              float* diag_w, float* diag_dmin, int* diag_argmin, hipStream_t s);
+bool validate_small_supported(int kind, int padded);
+hipError_t launch_validate_small(const StepArgs& P, int kind, int padded, const PointArgs& pts,
+                                 const float2* verts, const float4* rects, const float* Unew,
+                                 float* U, float* out, float* diag_unew, float* diag_dnom,
+                                 float* diag_jnom, hipStream_t s);
+
 // ---------------------------------------------------------------- batched path
 // Per-step arguments of one scene (refreshed by one host-to-device copy per
 // step, so a captured graph replays with new poses, seeds and nominals).
@@ -159,9 +182,10 @@ struct SceneDmin {
     unsigned int* key;
 };
 
-// One work item: pose tile [g0, g0 + blockDim) of SceneDmin sd, point chunk c.
+// One work item: pose tile [g0, g0 + blockDim) of SceneDmin sd against the
+// compacted points [c0, c1) (clipped to the valid count on the device).
 struct DminItem {
-    int sd, g0, c, pad;
+    int sd, g0, c0, c1;
 };
 
 // Register class of a footprint bucket (padded primitive count) in the

@@ -172,8 +172,8 @@ void k_dmin_persistent(const SceneDmin* __restrict__ sds, const DminItem* __rest
         const bool moving = S.pts.vx != nullptr;
         const float tau = moving ? pose_tau(S.pt, g) : 0.0f;
         const int nv = __builtin_amdgcn_readfirstlane(*S.pts.n_valid);
-        const int c0 = w.c * S.chunk;
-        const int c1 = min(c0 + S.chunk, nv);
+        const int c0 = w.c0;
+        const int c1 = min(w.c1, nv);
         float best;
         dmin_dispatch<CLS>(S, moving, q, tau, c0, c1, lds, best);
         if (live && (threadIdx.x & (L - 1)) == 0) atomicMin(&S.key[g], dkey(best));

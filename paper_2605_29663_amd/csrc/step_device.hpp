@@ -12,6 +12,11 @@ namespace emppi {
 constexpr int ROLL_HCHUNK = 16;                   // horizon steps per rollout chunk
 constexpr int ROLL_THREADS = WAVE * ROLL_HCHUNK;  // one (rollout, step) pair per thread
 constexpr int ROLL_LDS_FLOATS = 6 * WAVE * ROLL_HCHUNK;  // controls, headings, (cos, sin)
+// Rollouts per workgroup of the single-scene rollout kernel when K is small:
+// 16 rollouts x 16 steps = 256 threads, four times as many workgroups (and
+// compute units) as 64-rollout blocks, the same per-pair arithmetic.
+constexpr int ROLL_RB_SMALL = 16;
+constexpr int roll_lds_floats(int rb) { return 6 * rb * ROLL_HCHUNK; }
 constexpr int COST_THREADS = 1024;  // 64 rollouts x 16 horizon groups
 constexpr int FIN_THREADS = 128;    // one thread per horizon step
 constexpr int NOM_THREADS = 128;    // one thread per horizon step
@@ -97,26 +102,28 @@ __device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py
     return v;
 }
 
-// Sampling + rollouts of rollouts [r0, r0 + 64) (Algorithm 1 step 1), by
-// chunks of ROLL_HCHUNK horizon steps with ROLL_THREADS threads:
+// Sampling + rollouts of rollouts [r0, r0 + RB) (Algorithm 1 step 1), by
+// chunks of ROLL_HCHUNK horizon steps with RB * ROLL_HCHUNK threads:
 //   (a) thread (step hh, rollout l) draws the noise of its pair, clamps the
 //       sampled control (kept in LDS) and evaluates its heading rate;
-//   (b) wave 0, lane = rollout: the heading recursion (one fma per step);
+//   (b) the first RB threads, one per rollout: the heading recursion (one
+//       fma per step);
 //   (c) every thread: sin / cos of its pair's new heading;
-//   (d) wave 0: the position recursion, the scored poses and the distance
-//       keys' initial values;
-//   (e) every thread: the task + control terms of its pair, then wave 0 adds
-//       them up in step order.
-// lds: ROLL_LDS_FLOATS floats.
+//   (d) the first RB threads: the position recursion, the scored poses and
+//       the distance keys' initial values;
+//   (e) every thread: the task + control terms of its pair, then the first
+//       RB threads add them up in step order.
+// The result does not depend on RB.  lds: roll_lds_floats(RB) floats.
+template <int RB = WAVE>
 __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __restrict__ U,
                                               const RolloutOut& o, int r0, float* lds) {
     const int T = P.T, nu = P.nu, Kpad = P.Kpad;
     float* su = lds;                               // [hh][k][lane] sampled controls
-    float* sw = lds + 3 * WAVE * ROLL_HCHUNK;      // [hh][lane] heading rate, then heading
-    float2* scs = reinterpret_cast<float2*>(lds + 4 * WAVE * ROLL_HCHUNK);  // [hh][lane] (c, s)
-    const int lane = threadIdx.x & (WAVE - 1), hh = threadIdx.x / WAVE;
+    float* sw = lds + 3 * RB * ROLL_HCHUNK;        // [hh][lane] heading rate, then heading
+    float2* scs = reinterpret_cast<float2*>(lds + 4 * RB * ROLL_HCHUNK);  // [hh][lane] (c, s)
+    const int lane = threadIdx.x % RB, hh = threadIdx.x / RB;
     const int r = r0 + lane;
-    const bool chain = threadIdx.x < WAVE;
+    const bool chain = threadIdx.x < RB;
     float x = P.q0[0], y = P.q0[1], th = P.q0[2], s = 0.f, c = 1.f, jb = 0.0f;
     if (chain) seq_sincos(th, s, c);
     for (int h0 = 0; h0 < T; h0 += ROLL_HCHUNK) {
@@ -152,36 +159,36 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
                 // finite value (0 * NaN left over in reused memory is NaN)
                 for (int k = 0; k < nu; ++k) o.eps_ws[(h * nu + k) * Kpad + r] = 0.0f;
             }
-            for (int k = 0; k < 3; ++k) su[(hh * 3 + k) * WAVE + lane] = u[k];
-            sw[hh * WAVE + lane] = heading_rate(P.model, u, P.wheelbase);
+            for (int k = 0; k < 3; ++k) su[(hh * 3 + k) * RB + lane] = u[k];
+            sw[hh * RB + lane] = heading_rate(P.model, u, P.wheelbase);
         }
         __syncthreads();
         if (chain) {
             for (int k = 0; k < hn; ++k) {
-                th = heading_step(P.model, sw[k * WAVE + lane], P.dt, th);
-                sw[k * WAVE + lane] = th;
+                th = heading_step(P.model, sw[k * RB + lane], P.dt, th);
+                sw[k * RB + lane] = th;
             }
         }
         __syncthreads();
         if (hh < hn) {
             float sn, cn;
-            seq_sincos(sw[hh * WAVE + lane], sn, cn);
-            scs[hh * WAVE + lane] = make_float2(cn, sn);
+            seq_sincos(sw[hh * RB + lane], sn, cn);
+            scs[hh * RB + lane] = make_float2(cn, sn);
         }
         __syncthreads();
         if (chain) {
             for (int k = 0; k < hn; ++k) {
                 const int hk = h0 + k;
                 float u[3];
-                for (int q = 0; q < 3; ++q) u[q] = su[(k * 3 + q) * WAVE + lane];
+                for (int q = 0; q < 3; ++q) u[q] = su[(k * 3 + q) * RB + lane];
                 float4 pose = make_float4(x, y, c, s);
                 position_step(P.model, u, P.dt, s, c, x, y);
-                const float2 cs = scs[k * WAVE + lane];
+                const float2 cs = scs[k * RB + lane];
                 c = cs.x;
                 s = cs.y;
                 if (P.state_offset) pose = make_float4(x, y, c, s);
                 o.poses[hk * Kpad + r] = pose;
-                scs[k * WAVE + lane] = make_float2(pose.x, pose.y);  // scored position
+                scs[k * RB + lane] = make_float2(pose.x, pose.y);  // scored position
                 if (o.key) o.key[hk * Kpad + r] = DKEY_INIT;
                 if (o.key64) o.key64[hk * Kpad + r] = DKEY64_INIT;
                 if (o.diag_poses && r < P.K) {
@@ -195,14 +202,14 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
         }
         __syncthreads();
         if (hh < hn) {
-            const float2 p = scs[hh * WAVE + lane];
-            const float u[3] = {su[(hh * 3) * WAVE + lane], su[(hh * 3 + 1) * WAVE + lane],
-                                su[(hh * 3 + 2) * WAVE + lane]};
-            sw[hh * WAVE + lane] = task_ctrl(P, p.x, p.y, u);
+            const float2 p = scs[hh * RB + lane];
+            const float u[3] = {su[(hh * 3) * RB + lane], su[(hh * 3 + 1) * RB + lane],
+                                su[(hh * 3 + 2) * RB + lane]};
+            sw[hh * RB + lane] = task_ctrl(P, p.x, p.y, u);
         }
         __syncthreads();
         if (chain)
-            for (int k = 0; k < hn; ++k) jb += sw[k * WAVE + lane];
+            for (int k = 0; k < hn; ++k) jb += sw[k * RB + lane];
         __syncthreads();
     }
     if (chain) o.jbase[r] = jb;
@@ -263,52 +270,134 @@ __device__ __forceinline__ void cost_block(const StepArgs& P, const unsigned int
 
 // Deterministic block reductions (fixed butterfly within a wave, waves
 // combined in index order).  sh: 16 floats.
+// nw: the waves whose values are combined (every thread of the block must
+// call it; the block has at most 16 waves).
 template <typename Op>
-__device__ __forceinline__ float block_reduce(float v, float* sh, Op op) {
+__device__ __forceinline__ float block_reduce(float v, float* sh, Op op, int nw) {
     for (int o = WAVE / 2; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o));
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     __syncthreads();
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     float r = sh[0];
-    for (int w = 1; w < static_cast<int>(blockDim.x / WAVE); ++w) r = op(r, sh[w]);
+    for (int w = 1; w < nw; ++w) r = op(r, sh[w]);
     return r;
+}
+template <typename Op>
+__device__ __forceinline__ float block_reduce(float v, float* sh, Op op) {
+    return block_reduce(v, sh, op, static_cast<int>(blockDim.x / WAVE));
 }
 
 // Horizon step h of the path-integral update (Algorithm 1 step 3):
 // beta = min J~, omega = exp(-(J~ - beta)/lambda), U_h += (sum omega eps_h) /
-// (sum omega).  256 threads; every (scene, h) workgroup computes the same beta
-// and normaliser in the same order.
+// (sum omega).  The first NT threads do the work (NT = 0: every thread of the
+// 256-thread block); every (scene, h) workgroup computes the same beta and
+// normaliser in the same order.
+template <int NT = 0>
 __device__ __forceinline__ void update_block(const StepArgs& P, const float* __restrict__ jt,
                                              const float* __restrict__ eps_ws,
                                              const float* __restrict__ U, float* __restrict__ Unew,
                                              float* __restrict__ diag_w, int h, float* sh) {
     const int Kpad = P.Kpad, nu = P.nu;
+    const int nt = NT ? NT : static_cast<int>(blockDim.x);
+    const bool on = static_cast<int>(threadIdx.x) < nt;
     float b = INFINITY;
-    for (int r = threadIdx.x; r < Kpad; r += blockDim.x) b = fminf(b, jt[r]);
-    const float beta = block_reduce(b, sh, [](float a, float c) { return fminf(a, c); });
+    if (on)
+        for (int r = threadIdx.x; r < Kpad; r += nt) b = fminf(b, jt[r]);
+    const float beta = block_reduce(b, sh, [](float a, float c) { return fminf(a, c); }, nt / WAVE);
     float z = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
     const float* e0 = eps_ws + (h * nu) * Kpad;
-    for (int r = threadIdx.x; r < Kpad; r += blockDim.x) {
-        const float w = expf((beta - jt[r]) / P.lambda);
-        z += w;
-        n0 += w * e0[r];
-        if (nu > 1) n1 += w * e0[Kpad + r];
-        if (nu > 2) n2 += w * e0[2 * Kpad + r];
-    }
+    if (on)
+        for (int r = threadIdx.x; r < Kpad; r += nt) {
+            const float w = expf((beta - jt[r]) / P.lambda);
+            z += w;
+            n0 += w * e0[r];
+            if (nu > 1) n1 += w * e0[Kpad + r];
+            if (nu > 2) n2 += w * e0[2 * Kpad + r];
+        }
     auto add = [](float a, float c) { return a + c; };
-    const float Z = block_reduce(z, sh, add);
-    const float N0 = block_reduce(n0, sh, add);
-    const float N1 = nu > 1 ? block_reduce(n1, sh, add) : 0.f;
-    const float N2 = nu > 2 ? block_reduce(n2, sh, add) : 0.f;
+    const float Z = block_reduce(z, sh, add, nt / WAVE);
+    const float N0 = block_reduce(n0, sh, add, nt / WAVE);
+    const float N1 = nu > 1 ? block_reduce(n1, sh, add, nt / WAVE) : 0.f;
+    const float N2 = nu > 2 ? block_reduce(n2, sh, add, nt / WAVE) : 0.f;
     if (threadIdx.x == 0) {
         Unew[h * nu] = U[h * nu] + N0 / Z;
         if (nu > 1) Unew[h * nu + 1] = U[h * nu + 1] + N1 / Z;
         if (nu > 2) Unew[h * nu + 2] = U[h * nu + 2] + N2 / Z;
     }
-    if (diag_w && h == 0)
-        for (int r = threadIdx.x; r < P.K; r += blockDim.x)
-            diag_w[r] = expf((beta - jt[r]) / P.lambda) / Z;
+    if (diag_w && h == 0 && on)
+        for (int r = threadIdx.x; r < P.K; r += nt) diag_w[r] = expf((beta - jt[r]) / P.lambda) / Z;
+}
+
+// Cost and update fused for small K (one launch instead of two), with
+// COST_THREADS threads: every (horizon step h) workgroup first computes J~ of
+// all Kpad rollouts in cost_block's layout and operation order (thread (lane,
+// group q) sums the terms h' = q, q + 16, ... of rollout r0 + lane for every
+// 64-rollout slab r0; then per rollout the task and control terms plus the 16
+// partial sums in q order), so the bits are cost_block's; workgroup 0 also
+// stores them to jt and writes the d_min / argmin diagnostics; then the first
+// 256 threads run update_block for step h (the bits of the 256-thread
+// update).  LDS: sP 16 Kpad floats, sC 16 Kpad bytes, sJ Kpad floats.
+__device__ __forceinline__ void cost_update_block(const StepArgs& P,
+                                                  const unsigned int* __restrict__ key,
+                                                  const unsigned long long* __restrict__ key64,
+                                                  const float* __restrict__ jbase,
+                                                  const float* __restrict__ eps_ws,
+                                                  const float* __restrict__ U,
+                                                  float* __restrict__ Unew, float* __restrict__ jt,
+                                                  float* __restrict__ diag_w,
+                                                  float* __restrict__ diag_dmin,
+                                                  int* __restrict__ diag_argmin, int h, float* sP,
+                                                  unsigned char* sC, float* sJ, float* sh) {
+    constexpr int NGRP = COST_THREADS / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1), grp = threadIdx.x / WAVE;
+    const int Kpad = P.Kpad;
+    const bool first = h == 0;
+    for (int r0 = 0; r0 < Kpad; r0 += WAVE) {
+        const int r = r0 + lane;
+        float J = 0.0f;
+        int chi = 0;
+        if (r < P.K) {
+            for (int hh = grp; hh < P.T; hh += NGRP) {
+                const size_t g = static_cast<size_t>(hh) * Kpad + r;
+                float d;
+                int idx = -1;
+                if (key64) {
+                    const unsigned long long k = key64[g];
+                    d = dkey_distance(static_cast<unsigned int>(k >> 32));
+                    idx = static_cast<int>(static_cast<unsigned int>(k));
+                } else {
+                    d = dkey_distance(key[g]);
+                }
+                const float gap = fmaxf(P.d_safe - d, 0.0f);
+                J += (d < 0.0f ? P.w_coll : 0.0f) + P.w_rep * (gap * gap);
+                chi |= (d < P.d_safe) ? 1 : 0;
+                if (first && diag_dmin) diag_dmin[static_cast<size_t>(r) * P.T + hh] = d;
+                if (first && diag_argmin) diag_argmin[static_cast<size_t>(r) * P.T + hh] = idx;
+            }
+        }
+        sP[grp * Kpad + r] = J;
+        sC[grp * Kpad + r] = static_cast<unsigned char>(chi);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < Kpad; r += blockDim.x) {
+        float j;
+        if (r >= P.K) {
+            j = INFINITY;
+        } else {
+            float acc = jbase[r];
+            int any = 0;
+            for (int q = 0; q < NGRP; ++q) {
+                acc += sP[q * Kpad + r];
+                any |= sC[q * Kpad + r];
+            }
+            j = acc + (any ? P.w_inf : 0.0f);
+        }
+        sJ[r] = j;
+        if (first) jt[r] = j;
+    }
+    __syncthreads();
+    update_block<256>(P, sJ, eps_ws, U, Unew, diag_w, h, sh);
 }
 
 // Nominal trajectory of the updated sequence (Algorithm 1 step 4) in the same
