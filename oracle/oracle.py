@@ -33,10 +33,27 @@ PARAM_KEYS = ("K", "T", "nu", "model", "footprint_kind", "dt", "lambda_", "wheel
               "w_ctrl", "goal", "state_offset", "validate", "w_path", "path")
 
 
+# The same source built with AddressSanitizer and UndefinedBehaviorSanitizer
+# (every report fatal), for a run of the oracle's tests under the sanitizers:
+# load it with EXACT_MPPI_ORACLE_LIB=<path> and the sanitizer runtimes
+# preloaded into the (uninstrumented) Python process.
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+GCC_SAN_CMD = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+               "-fno-fast-math", "-fopenmp", "-shared", "-fPIC", "-Wall",
+               "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               "-o", _LIB_SAN, _SRC, "-lm"]
+
+
 def build() -> str:
     """Compile oracle.c with gcc into liboracle.so (always recompiles)."""
     subprocess.run(GCC_CMD, check=True)
     return _LIB
+
+
+def build_sanitized() -> str:
+    """Compile the sanitizer build liboracle_san.so (always recompiles)."""
+    subprocess.run(GCC_SAN_CMD, check=True)
+    return _LIB_SAN
 
 
 _lib = None
@@ -45,9 +62,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = os.environ.get("EXACT_MPPI_ORACLE_LIB") or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         d, i, l, vp = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
         u64, u32, f = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_float
         L.orc_seg_dist.restype = d
