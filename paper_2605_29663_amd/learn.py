@@ -43,8 +43,14 @@ def scene_params(sc, K):
     return p
 
 
-def corridor_scene(seed):
-    return scenes.scene_c2(seed=seed, clutter_keep=0.1)
+# Fraction of the in-corridor clutter kept in the proposal's scenes (the
+# corridor workload's generator draws 10 % of its points as uniform clutter;
+# 1.0 keeps all of it, 0.1 thins it so that most corridors stay traversable).
+CLUTTER_KEEP = 0.1
+
+
+def corridor_scene(seed, clutter_keep=None):
+    return scenes.scene_c2(seed=seed, clutter_keep=CLUTTER_KEEP if clutter_keep is None else clutter_keep)
 
 
 def make_context(sc):
@@ -65,8 +71,8 @@ def propagate(q, u, dt, L):
 class Episodes:
     """n corridor episodes stepped together with the batched plain MPPI step."""
 
-    def __init__(self, seeds, K):
-        self.scenes = [corridor_scene(s) for s in seeds]
+    def __init__(self, seeds, K, clutter_keep=None):
+        self.scenes = [corridor_scene(s, clutter_keep) for s in seeds]
         self.prms = [scene_params(sc, K) for sc in self.scenes]
         self.ctxs = [make_context(sc) for sc in self.scenes]
         self.batch = pkg.Batch(self.ctxs, self.prms)
@@ -91,7 +97,7 @@ class Episodes:
 
 
 def generate(n_samples, n_parallel=64, steps_per_episode=200, K=4096, seed0=TRAIN_SEED0,
-             net=None, log=print, max_seconds=None):
+             net=None, log=print, max_seconds=None, clutter_keep=None):
     """Features and updated nominals (M x T*nu, control units) of (up to)
     n_samples validated plain-MPPI steps, stopping early after max_seconds."""
     T = 40
@@ -101,7 +107,7 @@ def generate(n_samples, n_parallel=64, steps_per_episode=200, K=4096, seed0=TRAI
     have, ep = 0, 0
     t0 = time.time()
     while have < n_samples:
-        E = Episodes([seed0 + ep * n_parallel + s for s in range(n_parallel)], K)
+        E = Episodes([seed0 + ep * n_parallel + s for s in range(n_parallel)], K, clutter_keep)
         for t in range(steps_per_episode):
             qb, Ub, u, valid, Ua = E.step()
             for s in np.flatnonzero(valid):
@@ -184,7 +190,7 @@ def learned_update(net, ctx, prm, q, U_shift, seed, K, step=0, diag=True):
 
 
 def evaluate(net, n_states=1000, n_parallel=64, warm_steps=40, seed0=HELDOUT_SEED0,
-             K_big=4096, K_small=1024, repeats=4, log=print):
+             K_big=4096, K_small=1024, repeats=4, log=print, clutter_keep=None):
     """Held-out comparison.  For each state, `repeats` independent updates of
     each method (different noise seeds): (a) plain from the shifted nominal,
     K_big; (b) the same with K_small; (c) from the network's mean with
@@ -196,7 +202,7 @@ def evaluate(net, n_states=1000, n_parallel=64, warm_steps=40, seed0=HELDOUT_SEE
     ep = 0
     t0 = time.time()
     while len(rows) < n_states:
-        E = Episodes([seed0 + ep * n_parallel + s for s in range(n_parallel)], K_big)
+        E = Episodes([seed0 + ep * n_parallel + s for s in range(n_parallel)], K_big, clutter_keep)
         t = 0
         while len(rows) < n_states and t < warm_steps + 200:
             qb, Ub, u, valid, Ua = E.step()

@@ -19,7 +19,8 @@ def main():
     ap.add_argument("--samples", type=int, default=50000)
     ap.add_argument("--parallel", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--eval-states", type=int, default=1000)
+    ap.add_argument("--eval-states", type=int, default=1000,
+                    help="held-out states to evaluate (0: train only)")
     ap.add_argument("--out", default=".")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-data-seconds", type=float, default=420.0)
@@ -28,6 +29,11 @@ def main():
     ap.add_argument("--repeats", type=int, default=4)
     ap.add_argument("--absolute", action="store_true",
                     help="train on absolute sequences instead of residual corrections")
+    ap.add_argument("--clutter-keep", type=float, default=None,
+                    help="fraction of the corridor clutter kept in training and evaluation "
+                         "scenes (default: the module's CLUTTER_KEEP)")
+    ap.add_argument("--warm-steps", type=int, default=40,
+                    help="closed-loop steps before the first evaluated state of an episode")
     args = ap.parse_args()
     import torch
     import paper_2605_29663_amd as pkg
@@ -45,7 +51,7 @@ def main():
         t1 = t2 = time.time()
     else:
         X, U_upd = learn.generate(args.samples, n_parallel=args.parallel, net=net, log=log,
-                                  max_seconds=args.max_data_seconds)
+                                  max_seconds=args.max_data_seconds, clutter_keep=args.clutter_keep)
         n_samples = int(X.shape[0])
         log(f"data: {n_samples} samples in {time.time() - t0:.0f} s")
         Y, scale = learn.make_targets(net, X, U_upd, residual=not args.absolute)
@@ -56,13 +62,19 @@ def main():
         log(f"train: {time.time() - t1:.0f} s, final loss {losses[-1]:.5f}")
         net.save(os.path.join(args.out, "proposal_c2.bin"))
         t2 = time.time()
-    costs, fallback = learn.evaluate(net, n_states=args.eval_states, n_parallel=args.parallel,
-                                     repeats=args.repeats, log=log)
-    summary = learn.summarize(costs, fallback)
+    summary = {}
+    if args.eval_states > 0:
+        costs, fallback = learn.evaluate(net, n_states=args.eval_states, n_parallel=args.parallel,
+                                         repeats=args.repeats, log=log, clutter_keep=args.clutter_keep,
+                                         warm_steps=args.warm_steps)
+        summary = learn.summarize(costs, fallback)
+        summary.update(per_state_costs=costs.tolist(), fallback=fallback.tolist())
     summary.update(samples=n_samples, epochs=args.epochs, train_loss=losses, repeats=args.repeats,
-                   per_state_costs=costs.tolist(), fallback=fallback.tolist(),
+                   clutter_keep=learn.CLUTTER_KEEP if args.clutter_keep is None else args.clutter_keep,
+                   warm_steps=args.warm_steps,
                    seconds={"data": t1 - t0, "train": t2 - t1, "eval": time.time() - t2})
-    with open(os.path.join(args.out, "proposal_c2_eval.json"), "w") as f:
+    name = "proposal_c2_eval.json" if args.eval_states > 0 else "proposal_c2_train.json"
+    with open(os.path.join(args.out, name), "w") as f:
         json.dump(summary, f, indent=1)
     log(json.dumps({k: v for k, v in summary.items()
                     if k not in ("train_loss", "per_state_costs", "fallback")}))
