@@ -382,20 +382,38 @@ def run_batched(args):
     from paper_2605_29663_amd import scenes
 
     cases = scenes.batch_scenes(64)
-    ctxs = []
+    setup = {}
+    tl = time.perf_counter()
+    pkg.load()
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    setup["library_load_and_device_init_s"] = time.perf_counter() - tl
+    ctxs, t_fp = [], []
+    ts = time.perf_counter()
     for prm, sc in cases:
         c = pkg.Context(0)
+        tf = time.perf_counter()
         c.set_footprint(pkg.POLYGON, sc["polygon"])
+        t_fp.append(time.perf_counter() - tf)
         c.set_points(sc["ox"], sc["oy"])
         ctxs.append(c)
+    setup["contexts_footprints_points_s"] = time.perf_counter() - ts
+    setup["set_footprint_ms_mean"] = float(np.mean(t_fp) * 1e3)
+    ts = time.perf_counter()
     b = pkg.Batch(ctxs, [p for p, _ in cases])
+    setup["batch_create_s"] = time.perf_counter() - ts
+    ts = time.perf_counter()
     work = b.mppi_batch_autotune(reps=2)
+    setup["batch_autotune_s"] = time.perf_counter() - ts
     n = len(cases)
     U = b.new_nominals()
     q0 = np.zeros((n, 3), np.float32)
     seeds = np.arange(1000, 1000 + n, dtype=np.uint64)
     for i in range(args.warmup):
+        ts = time.perf_counter()
         b.mppi_step_batched(q0, U, seeds, np.full(n, i, np.uint64), use_graph=True)
+        if i == 0:
+            setup["first_graph_step_incl_capture_s"] = time.perf_counter() - ts
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
@@ -446,6 +464,7 @@ def run_batched(args):
                      "timing": "HIP events around the persistent launches of eager steps",
                      "tiles": {"pairs_per_item": work, "items_main": items_main,
                                "items_validation": items_val, "source": "batch autotuner"}},
+        "setup": setup,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(cases, pairs_step, max(1, 2 * args.cpu_reps))
@@ -538,9 +557,21 @@ def main():
     geom = sc["polygon"] if kind == 0 else sc["rects"]
     P = len(geom)
 
+    setup = {}
+    tl = time.perf_counter()
+    pkg.load()
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    setup["library_load_and_device_init_s"] = time.perf_counter() - tl
+    ts = time.perf_counter()
     ctx = pkg.Context(0)
+    setup["context_create_ms"] = (time.perf_counter() - ts) * 1e3
+    ts = time.perf_counter()
     ctx.set_footprint(kind, geom)
+    setup["set_footprint_ms"] = (time.perf_counter() - ts) * 1e3
+    ts = time.perf_counter()
     ctx.set_points(sc["ox"], sc["oy"], sc.get("ovx"), sc.get("ovy"), sc.get("valid"))
+    setup["set_points_ms"] = (time.perf_counter() - ts) * 1e3
     U = torch.zeros((T, nu), dtype=torch.float32, device="cuda")
     params = pkg.make_params(prm)
     q0 = (0.0, 0.0, 0.0)
@@ -557,12 +588,17 @@ def main():
         tuned = (int(shipped[0][5]), int(shipped[0][6]))
         tile_source = "shipped table"
     else:
+        ts = time.perf_counter()
         tuned = ctx.mppi_autotune(None, reps=3, params=params)
+        setup["autotune_s"] = time.perf_counter() - ts
         tile_source = "autotuned in this run"
     if args.graph:
         ctx.mppi_set_graph(True)
     for i in range(args.warmup):
+        ts = time.perf_counter()
         ctx.mppi_step(None, q0, U, seed, i, params=params)
+        if i == 0:
+            setup["first_step_s"] = time.perf_counter() - ts
     torch.cuda.synchronize()
     if not args.graph:
         ctx.mppi_set_profiling(True)
@@ -632,6 +668,7 @@ def main():
                      "kernel_ms": k_avg_ms, "launches": k_n,
                      "tiles": ({"source": "batch autotuner (queue item size)"} if args.graph else
                                {"block": tuned[0], "chunks": tuned[1], "source": tile_source})},
+        "setup": setup,
     }
 
     if not args.no_cpu_baseline:

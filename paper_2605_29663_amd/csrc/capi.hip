@@ -70,8 +70,11 @@ int mppi_create(mppi_ctx* out, int device, void* hip_stream) {
     DeviceGuard g(device);
     e = ctx->n_valid.ensure(sizeof(int));
     if (e == hipSuccess) e = ctx->path.ensure(MPPI_MAX_PATH * sizeof(float2));
-    if (e == hipSuccess) e = ctx->out.ensure(OUT_FLOATS * sizeof(float));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_out), OUT_FLOATS * sizeof(float), 0);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&ctx->h_res), OUT_FLOATS * sizeof(float),
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->d_res), ctx->h_res, 0);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->n_valid.p, 0, sizeof(int), ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e == hipSuccess) e = scratch_lookup(device);  // the device is current (DeviceGuard)
@@ -95,9 +98,10 @@ int mppi_destroy(mppi_ctx ctx) {
                           &ctx->cloud_r2, &ctx->cloud_flag, &ctx->cloud_excl, &ctx->cloud_misc,
                           &ctx->eps_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
                           &ctx->key, &ctx->key64, &ctx->unew, &ctx->nom_poses,
-                          &ctx->key_nom, &ctx->out};
+                          &ctx->key_nom};
         for (DevBuf* b : bufs) b->release();
         if (ctx->h_out) (void)hipHostFree(ctx->h_out);
+        if (ctx->h_res) (void)hipHostFree(ctx->h_res);
         if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
         if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     }
@@ -495,8 +499,7 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
         // nominal, its distances and validation in one single-workgroup launch
         HIP_TRY(ctx, launch_validate_small(A, kind, padded, point_args(ctx), ctx->poly_verts.as<float2>(),
                                            ctx->rects.as<float4>(), ctx->unew.as<float>(), dU,
-                                           ctx->out.as<float>(), D.U_upd, D.d_nom, D.J_nom,
-                                           ctx->stream));
+                                           ctx->d_res, D.U_upd, D.d_nom, D.J_nom, ctx->stream));
     } else if (prm->validate) {
         HIP_TRY(ctx, ctx->nom_poses.ensure(sizeof(float4) * T));
         HIP_TRY(ctx, launch_nominal(A, ctx->unew.as<float>(), ctx->nom_poses.as<float4>(),
@@ -506,15 +509,16 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
                               ctx->key_nom.as<unsigned int>(), nullptr))
             return rc;
         HIP_TRY(ctx, launch_finalize(A, 1, ctx->key_nom.as<unsigned int>(), ctx->nom_poses.as<float4>(),
-                                     ctx->unew.as<float>(), dU, ctx->out.as<float>(), D.U_upd, D.d_nom,
+                                     ctx->unew.as<float>(), dU, ctx->d_res, D.U_upd, D.d_nom,
                                      D.J_nom, ctx->stream));
     } else {
         HIP_TRY(ctx, launch_finalize(A, 0, ctx->key_nom.as<unsigned int>(), ctx->nom_poses.as<float4>(),
-                                     ctx->unew.as<float>(), dU, ctx->out.as<float>(), D.U_upd, D.d_nom,
+                                     ctx->unew.as<float>(), dU, ctx->d_res, D.U_upd, D.d_nom,
                                      D.J_nom, ctx->stream));
     }
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_out, ctx->out.p, OUT_FLOATS * sizeof(float), hipMemcpyDeviceToHost,
-                                ctx->stream));
+    // the finalising kernel wrote the result record into ctx->h_res
+    // (device-mapped coherent host memory); the synchronisation makes it
+    // visible here
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->prof) {
         float ms = 0.f;
@@ -522,8 +526,8 @@ int mppi_step(mppi_ctx ctx, const mppi_params* prm, const float* q0, float* dU, 
         ctx->prof_ms += ms;
         ctx->prof_n += 1;
     }
-    for (int c = 0; c < prm->nu; ++c) u_out[c] = ctx->h_out[c];
-    if (valid_out) *valid_out = ctx->h_out[3] != 0.0f;
+    for (int c = 0; c < prm->nu; ++c) u_out[c] = ctx->h_res[c];
+    if (valid_out) *valid_out = ctx->h_res[3] != 0.0f;
     return MPPI_OK;
 }
 

@@ -92,8 +92,14 @@ struct mppi_ctx_s {
     // point-cloud pre-processing workspace
     DevBuf cloud_keys, cloud_first, cloud_cell, cloud_r2, cloud_flag, cloud_excl, cloud_misc;
     // step workspaces
-    DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom, out;
+    DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom;
     float* h_out = nullptr;  // pinned
+    // the step's result record (u*, valid, J_nom), written by the last
+    // kernel of a step straight into pinned, device-mapped, coherent host
+    // memory (no device-to-host copy on the critical path): host address and
+    // the device's address of the same memory
+    float* h_res = nullptr;
+    float* d_res = nullptr;
     // tile shapes picked by mppi_autotune, keyed by (kind, padded, moving, npose, n)
     std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> tuned;
     int force_block = 0, force_nchunk = 0;  // mppi_set_tiles

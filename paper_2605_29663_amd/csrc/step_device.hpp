@@ -11,26 +11,32 @@ namespace emppi {
 
 constexpr int ROLL_HCHUNK = 16;                   // horizon steps per rollout chunk
 constexpr int ROLL_THREADS = WAVE * ROLL_HCHUNK;  // one (rollout, step) pair per thread
-constexpr int ROLL_LDS_FLOATS = 6 * WAVE * ROLL_HCHUNK;  // controls, headings, (cos, sin)
+// LDS of a rollout workgroup of rb rollouts, per (step, rollout) pair: the
+// heading rate / heading / task terms, (cos, sin) of the heading, and the
+// planar velocity / position.
+constexpr int roll_lds_floats(int rb) { return 5 * rb * ROLL_HCHUNK; }
+constexpr int ROLL_LDS_FLOATS = roll_lds_floats(WAVE);
 // Rollouts per workgroup of the single-scene rollout kernel when K is small:
 // 16 rollouts x 16 steps = 256 threads, four times as many workgroups (and
 // compute units) as 64-rollout blocks, the same per-pair arithmetic.
 constexpr int ROLL_RB_SMALL = 16;
-constexpr int roll_lds_floats(int rb) { return 6 * rb * ROLL_HCHUNK; }
 constexpr int COST_THREADS = 1024;  // 64 rollouts x 16 horizon groups
 constexpr int FIN_THREADS = 128;    // one thread per horizon step
 constexpr int NOM_THREADS = 128;    // one thread per horizon step
-constexpr int NOM_LDS_FLOATS = 6 * MPPI_MAX_T_DEV;
+constexpr int NOM_LDS_FLOATS = 5 * MPPI_MAX_T_DEV;
 
 // One forward-Euler step q_{h+1} = q_h + F_m(q_h, u_h) dt (Section "Robot
 // Kinematic Models") in the fixed single-precision sequence, split into the
 // heading recursion theta_{h+1} = theta_h + omega(u_h) dt (which does not
-// depend on the position) and the position update, which uses (s, c) = sin /
-// cos of theta_h.  "a += b dt" is one fma(b, dt, a).  Splitting the two lets
-// the costly sin/cos and tan of every step run in parallel while the serial
-// recursions are single fma chains; the values are the same as a plain
-// step-by-step integration.
+// depend on the position) and the position recursion p_{h+1} = p_h +
+// v(u_h, theta_h) dt, where the planar velocity v uses (s, c) = sin / cos of
+// theta_h.  "a += b dt" is one fma(b, dt, a).  Splitting them lets the
+// costly sin / cos and tan and the velocities of every step run in parallel,
+// while each serial recursion is a chain of fmas on values read into
+// registers ahead of it; the values are those of a plain step-by-step
+// integration.
 __device__ __forceinline__ bool model_rotates(int model) { return model <= 3; }
+__device__ __forceinline__ bool model_translates(int model) { return model != 3; }
 
 __device__ __forceinline__ float heading_rate(int model, const float u[3], float L) {
     switch (model) {
@@ -42,32 +48,54 @@ __device__ __forceinline__ float heading_rate(int model, const float u[3], float
     }
 }
 
-__device__ __forceinline__ float heading_step(int model, float w, float dt, float th) {
-    return model_rotates(model) ? __builtin_fmaf(w, dt, th) : th;
-}
-
-__device__ __forceinline__ void position_step(int model, const float u[3], float dt, float s,
-                                              float c, float& x, float& y) {
+// Planar velocity of a translating model at heading (s, c) = (sin, cos).
+__device__ __forceinline__ float2 planar_velocity(int model, const float u[3], float s, float c) {
     switch (model) {
     case 0:
-    case 1:
-        x = __builtin_fmaf(u[0] * c, dt, x);
-        y = __builtin_fmaf(u[0] * s, dt, y);
-        break;
-    case 2: {
-        const float xd = __builtin_fmaf(u[0], c, -(u[1] * s));
-        const float yd = __builtin_fmaf(u[0], s, u[1] * c);
-        x = __builtin_fmaf(xd, dt, x);
-        y = __builtin_fmaf(yd, dt, y);
-        break;
+    case 1: return make_float2(u[0] * c, u[0] * s);
+    case 2: return make_float2(__builtin_fmaf(u[0], c, -(u[1] * s)), __builtin_fmaf(u[0], s, u[1] * c));
+    default: return make_float2(-(u[0] * s), u[0] * c);  // parallel: along the body y axis
     }
-    case 3:
-        break;
-    default:  // parallel (v_para): translation along the body y axis
-        x = __builtin_fmaf(-(u[0] * s), dt, x);
-        y = __builtin_fmaf(u[0] * c, dt, y);
-        break;
-    }
+}
+
+// Serial recursions over n <= ROLL_HCHUNK steps whose per-step inputs sit in
+// LDS at a[k * stride] (k < n): every input is read into a register first,
+// then the fma chain runs and each state is written back over its input.
+__device__ __forceinline__ float heading_chain(float* a, int stride, int n, float dt, float th) {
+    float w[ROLL_HCHUNK];
+#pragma unroll
+    for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = k < n ? a[k * stride] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < ROLL_HCHUNK; ++k)
+        if (k < n) {
+            th = __builtin_fmaf(w[k], dt, th);
+            a[k * stride] = th;
+        }
+    return th;
+}
+
+__device__ __forceinline__ void position_chain(float2* a, int stride, int n, float dt, float& x,
+                                               float& y) {
+    float2 v[ROLL_HCHUNK];
+#pragma unroll
+    for (int k = 0; k < ROLL_HCHUNK; ++k) v[k] = k < n ? a[k * stride] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < ROLL_HCHUNK; ++k)
+        if (k < n) {
+            x = __builtin_fmaf(v[k].x, dt, x);
+            y = __builtin_fmaf(v[k].y, dt, y);
+            a[k * stride] = make_float2(x, y);
+        }
+}
+
+__device__ __forceinline__ float sum_chain(const float* a, int stride, int n, float acc) {
+    float w[ROLL_HCHUNK];
+#pragma unroll
+    for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = k < n ? a[k * stride] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < ROLL_HCHUNK; ++k)
+        if (k < n) acc += w[k];
+    return acc;
 }
 
 // Distance of (px, py) to the guidance polyline: min over its segments of
@@ -103,34 +131,39 @@ __device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py
 }
 
 // Sampling + rollouts of rollouts [r0, r0 + RB) (Algorithm 1 step 1), by
-// chunks of ROLL_HCHUNK horizon steps with RB * ROLL_HCHUNK threads:
-//   (a) thread (step hh, rollout l) draws the noise of its pair, clamps the
-//       sampled control (kept in LDS) and evaluates its heading rate;
-//   (b) the first RB threads, one per rollout: the heading recursion (one
-//       fma per step);
-//   (c) every thread: sin / cos of its pair's new heading;
-//   (d) the first RB threads: the position recursion, the scored poses and
-//       the distance keys' initial values;
-//   (e) every thread: the task + control terms of its pair, then the first
-//       RB threads add them up in step order.
+// chunks of ROLL_HCHUNK horizon steps with RB * ROLL_HCHUNK threads; thread
+// (step hh, rollout l) keeps its pair's control in registers:
+//   (a) every thread draws the noise of its pair, clamps the sampled control
+//       and evaluates its heading rate;
+//   (b) the first RB threads (hh = 0), one per rollout: the heading
+//       recursion;
+//   (c) every thread: sin / cos of its pair's new heading, then (d) the
+//       planar velocity at the heading before its step;
+//   (e) the first RB threads: the position recursion;
+//   (f) every thread: its pair's scored pose, the distance keys' initial
+//       values and the task + control terms, which the first RB threads then
+//       add up in step order.
 // The result does not depend on RB.  lds: roll_lds_floats(RB) floats.
 template <int RB = WAVE>
 __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __restrict__ U,
                                               const RolloutOut& o, int r0, float* lds) {
     const int T = P.T, nu = P.nu, Kpad = P.Kpad;
-    float* su = lds;                               // [hh][k][lane] sampled controls
-    float* sw = lds + 3 * RB * ROLL_HCHUNK;        // [hh][lane] heading rate, then heading
-    float2* scs = reinterpret_cast<float2*>(lds + 4 * RB * ROLL_HCHUNK);  // [hh][lane] (c, s)
+    float* sw = lds;  // [hh][lane] heading rate, then heading, then task + control terms
+    float2* scs = reinterpret_cast<float2*>(lds + RB * ROLL_HCHUNK);      // [hh][lane] (c, s) after step
+    float2* sxy = reinterpret_cast<float2*>(lds + 3 * RB * ROLL_HCHUNK);  // [hh][lane] velocity, then position after step
     const int lane = threadIdx.x % RB, hh = threadIdx.x / RB;
     const int r = r0 + lane;
-    const bool chain = threadIdx.x < RB;
+    const bool chain = threadIdx.x < RB;  // hh == 0
+    const bool rotates = model_rotates(P.model), translates = model_translates(P.model);
+    // chain threads: the state at the start of the chunk
     float x = P.q0[0], y = P.q0[1], th = P.q0[2], s = 0.f, c = 1.f, jb = 0.0f;
     if (chain) seq_sincos(th, s, c);
     for (int h0 = 0; h0 < T; h0 += ROLL_HCHUNK) {
         const int hn = min(ROLL_HCHUNK, T - h0);
         const int h = h0 + hh;
-        if (hh < hn) {
-            float u[3] = {0.f, 0.f, 0.f};
+        const bool act = hh < hn;
+        float u[3] = {0.f, 0.f, 0.f};
+        if (act) {
             if (r < P.K && o.useq) {
                 // a given sequence, clamped to the control box, no noise
                 for (int k = 0; k < nu; ++k) {
@@ -159,57 +192,69 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
                 // finite value (0 * NaN left over in reused memory is NaN)
                 for (int k = 0; k < nu; ++k) o.eps_ws[(h * nu + k) * Kpad + r] = 0.0f;
             }
-            for (int k = 0; k < 3; ++k) su[(hh * 3 + k) * RB + lane] = u[k];
             sw[hh * RB + lane] = heading_rate(P.model, u, P.wheelbase);
         }
         __syncthreads();
         if (chain) {
-            for (int k = 0; k < hn; ++k) {
-                th = heading_step(P.model, sw[k * RB + lane], P.dt, th);
-                sw[k * RB + lane] = th;
+            if (rotates) {
+                th = heading_chain(sw + lane, RB, hn, P.dt, th);
+            } else {
+                for (int k = 0; k < hn; ++k) sw[k * RB + lane] = th;
             }
         }
         __syncthreads();
-        if (hh < hn) {
-            float sn, cn;
+        float cn = 1.f, sn = 0.f;
+        if (act) {
             seq_sincos(sw[hh * RB + lane], sn, cn);
             scs[hh * RB + lane] = make_float2(cn, sn);
         }
         __syncthreads();
+        // heading before the step: the chain's state for hh = 0
+        float cb = c, sb = s;
+        if (act && hh > 0) {
+            const float2 p = scs[(hh - 1) * RB + lane];
+            cb = p.x;
+            sb = p.y;
+        }
+        if (act && translates) sxy[hh * RB + lane] = planar_velocity(P.model, u, sb, cb);
+        __syncthreads();
+        const float xs = x, ys = y;
         if (chain) {
-            for (int k = 0; k < hn; ++k) {
-                const int hk = h0 + k;
-                float u[3];
-                for (int q = 0; q < 3; ++q) u[q] = su[(k * 3 + q) * RB + lane];
-                float4 pose = make_float4(x, y, c, s);
-                position_step(P.model, u, P.dt, s, c, x, y);
-                const float2 cs = scs[k * RB + lane];
-                c = cs.x;
-                s = cs.y;
-                if (P.state_offset) pose = make_float4(x, y, c, s);
-                o.poses[hk * Kpad + r] = pose;
-                scs[k * RB + lane] = make_float2(pose.x, pose.y);  // scored position
-                if (o.key) o.key[hk * Kpad + r] = DKEY_INIT;
-                if (o.key64) o.key64[hk * Kpad + r] = DKEY64_INIT;
-                if (o.diag_poses && r < P.K) {
-                    float* dp = o.diag_poses + (static_cast<size_t>(r) * T + hk) * 4;
-                    dp[0] = pose.x;
-                    dp[1] = pose.y;
-                    dp[2] = pose.z;
-                    dp[3] = pose.w;
-                }
+            if (translates) {
+                position_chain(sxy + lane, RB, hn, P.dt, x, y);
+            } else {
+                for (int k = 0; k < hn; ++k) sxy[k * RB + lane] = make_float2(x, y);
             }
+            const float2 e = scs[(hn - 1) * RB + lane];
+            c = e.x;
+            s = e.y;
         }
         __syncthreads();
-        if (hh < hn) {
-            const float2 p = scs[hh * RB + lane];
-            const float u[3] = {su[(hh * 3) * RB + lane], su[(hh * 3 + 1) * RB + lane],
-                                su[(hh * 3 + 2) * RB + lane]};
-            sw[hh * RB + lane] = task_ctrl(P, p.x, p.y, u);
+        if (act) {
+            float4 pose;
+            if (P.state_offset) {
+                const float2 p = sxy[hh * RB + lane];
+                pose = make_float4(p.x, p.y, cn, sn);
+            } else if (hh > 0) {
+                const float2 p = sxy[(hh - 1) * RB + lane];
+                pose = make_float4(p.x, p.y, cb, sb);
+            } else {
+                pose = make_float4(xs, ys, cb, sb);
+            }
+            o.poses[h * Kpad + r] = pose;
+            if (o.key) o.key[h * Kpad + r] = DKEY_INIT;
+            if (o.key64) o.key64[h * Kpad + r] = DKEY64_INIT;
+            if (o.diag_poses && r < P.K) {
+                float* dp = o.diag_poses + (static_cast<size_t>(r) * T + h) * 4;
+                dp[0] = pose.x;
+                dp[1] = pose.y;
+                dp[2] = pose.z;
+                dp[3] = pose.w;
+            }
+            sw[hh * RB + lane] = task_ctrl(P, pose.x, pose.y, u);
         }
         __syncthreads();
-        if (chain)
-            for (int k = 0; k < hn; ++k) jb += sw[k * RB + lane];
+        if (chain) jb = sum_chain(sw + lane, RB, hn, jb);
         __syncthreads();
     }
     if (chain) o.jbase[r] = jb;
@@ -402,51 +447,77 @@ __device__ __forceinline__ void cost_update_block(const StepArgs& P,
 
 // Nominal trajectory of the updated sequence (Algorithm 1 step 4) in the same
 // single-precision sequence as the sampled rollouts, with NOM_THREADS threads
-// (thread h = horizon step h): heading rates in parallel, the heading
-// recursion on thread 0, sin / cos in parallel, the position recursion on
-// thread 0.  The distance keys of the T nominal poses are initialised on the
-// way.  lds: NOM_LDS_FLOATS floats.
+// (thread h = horizon step h, holding u_h): heading rates in parallel, the
+// heading recursion on thread 0, sin / cos and the planar velocities in
+// parallel, the position recursion on thread 0 (both recursions in chunks
+// of ROLL_HCHUNK steps read into registers), the poses in parallel.  The
+// distance keys of the T nominal poses are initialised on the way.  Every
+// thread returns after the poses are written (no barrier after them).
+// lds: NOM_LDS_FLOATS floats.
 __device__ __forceinline__ void nominal_block(const StepArgs& P, const float* __restrict__ Unew,
                                               float4* __restrict__ nom,
                                               unsigned int* __restrict__ key_nom, float* lds) {
     const int T = P.T, nu = P.nu, h = threadIdx.x;
-    float* su = lds;                          // [h][3]
-    float* sw = lds + 3 * MPPI_MAX_T_DEV;     // heading rate, then heading after step h
-    float2* scs = reinterpret_cast<float2*>(lds + 4 * MPPI_MAX_T_DEV);
-    if (h < T) {
-        float u[3] = {0.f, 0.f, 0.f};
+    const bool act = h < T;
+    float* sw = lds;                                                     // heading rate, then heading after step h
+    float2* scs = reinterpret_cast<float2*>(lds + MPPI_MAX_T_DEV);      // (c, s) after step h
+    float2* sxy = reinterpret_cast<float2*>(lds + 3 * MPPI_MAX_T_DEV);  // velocity, then position after step h
+    float u[3] = {0.f, 0.f, 0.f};
+    if (act) {
         for (int k = 0; k < nu; ++k) u[k] = Unew[h * nu + k];
-        for (int k = 0; k < 3; ++k) su[h * 3 + k] = u[k];
         sw[h] = heading_rate(P.model, u, P.wheelbase);
         key_nom[h] = DKEY_INIT;
     }
     __syncthreads();
     if (h == 0) {
         float th = P.q0[2];
-        for (int k = 0; k < T; ++k) {
-            th = heading_step(P.model, sw[k], P.dt, th);
-            sw[k] = th;
+        for (int k0 = 0; k0 < T; k0 += ROLL_HCHUNK) {
+            const int n = min(ROLL_HCHUNK, T - k0);
+            if (model_rotates(P.model))
+                th = heading_chain(sw + k0, 1, n, P.dt, th);
+            else
+                for (int k = 0; k < n; ++k) sw[k0 + k] = th;
         }
     }
     __syncthreads();
-    if (h < T) {
-        float sn, cn;
+    float cn = 1.f, sn = 0.f;
+    if (act) {
         seq_sincos(sw[h], sn, cn);
         scs[h] = make_float2(cn, sn);
     }
     __syncthreads();
-    if (h != 0) return;
-    float x = P.q0[0], y = P.q0[1], s, c;
-    seq_sincos(P.q0[2], s, c);
-    for (int k = 0; k < T; ++k) {
-        const float u[3] = {su[k * 3], su[k * 3 + 1], su[k * 3 + 2]};
-        float4 pose = make_float4(x, y, c, s);
-        position_step(P.model, u, P.dt, s, c, x, y);
-        const float2 cs = scs[k];
-        c = cs.x;
-        s = cs.y;
-        if (P.state_offset) pose = make_float4(x, y, c, s);
-        nom[k] = pose;
+    float cb, sb;  // heading before step h
+    if (h == 0) {
+        seq_sincos(P.q0[2], sb, cb);
+    } else if (act) {
+        const float2 p = scs[h - 1];
+        cb = p.x;
+        sb = p.y;
+    }
+    const bool translates = model_translates(P.model);
+    if (act && translates) sxy[h] = planar_velocity(P.model, u, sb, cb);
+    __syncthreads();
+    if (h == 0) {
+        float x = P.q0[0], y = P.q0[1];
+        for (int k0 = 0; k0 < T; k0 += ROLL_HCHUNK) {
+            const int n = min(ROLL_HCHUNK, T - k0);
+            if (translates)
+                position_chain(sxy + k0, 1, n, P.dt, x, y);
+            else
+                for (int k = 0; k < n; ++k) sxy[k0 + k] = make_float2(x, y);
+        }
+    }
+    __syncthreads();
+    if (act) {
+        if (P.state_offset) {
+            const float2 p = sxy[h];
+            nom[h] = make_float4(p.x, p.y, cn, sn);
+        } else if (h > 0) {
+            const float2 p = sxy[h - 1];
+            nom[h] = make_float4(p.x, p.y, cb, sb);
+        } else {
+            nom[h] = make_float4(P.q0[0], P.q0[1], cb, sb);
+        }
     }
 }
 
