@@ -600,8 +600,6 @@ def main():
         if i == 0:
             setup["first_step_s"] = time.perf_counter() - ts
     torch.cuda.synchronize()
-    if not args.graph:
-        ctx.mppi_set_profiling(True)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -611,13 +609,17 @@ def main():
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if args.graph:
-        # the distance pass of the same one-scene batch timed on as many
-        # eager steps (a graph replay cannot be bracketed per launch)
-        ctx.mppi_set_profiling(True)
-        for i in range(args.steps):
-            ctx.mppi_step(None, q0, U, seed, args.warmup + args.steps + i, params=params)
-        torch.cuda.synchronize()
+    # the distance kernel timed with HIP events (recorded on the library's
+    # stream around each launch) over as many steps right after the timed
+    # region: the two event records per step add launch gaps that the
+    # latency above should not carry (a graph replay cannot be bracketed per
+    # launch at all)
+    ctx.mppi_set_profiling(True)
+    tp0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.mppi_step(None, q0, U, seed, args.warmup + args.steps + i, params=params)
+    torch.cuda.synchronize()
+    ms_step_events = (time.perf_counter() - tp0) * 1e3 / args.steps
     k_ms, k_n = ctx.mppi_get_profile()
     ctx.mppi_set_profiling(False)
 
@@ -666,6 +668,8 @@ def main():
                      "traffic": (None if args.graph or args.polygon_vertices else
                                  traffic_record(workload)),
                      "kernel_ms": k_avg_ms, "launches": k_n,
+                     "timing": "HIP events around every distance launch of as many steps right after "
+                               "the timed region (%.4f ms per step with the events)" % ms_step_events,
                      "tiles": ({"source": "batch autotuner (queue item size)"} if args.graph else
                                {"block": tuned[0], "chunks": tuned[1], "source": tile_source})},
         "setup": setup,

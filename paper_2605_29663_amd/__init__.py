@@ -230,6 +230,7 @@ class Context:
             raise MppiError(rc, self.lib.mppi_last_error(None).decode())
         self.h = h
         self._keep = []
+        self._step_bufs = ((ctypes.c_float * 3)(), (ctypes.c_float * 3)(), ctypes.c_int(0))
 
     def close(self):
         if getattr(self, "h", None):
@@ -416,10 +417,10 @@ class Context:
             if diag is not True:
                 out = {k: v for k, v in out.items() if k in set(diag)}
             D = MppiDiag(*[out[k].data_ptr() if k in out else None for k in MppiDiag.names()])
-        q = (ctypes.c_float * 3)(*[float(v) for v in q0])
-        u_out = (ctypes.c_float * 3)()
-        valid = ctypes.c_int(0)
-        self._check(self.lib.mppi_step(self.h, ctypes.byref(p), q, _ptr(U), int(seed), int(step),
+        # per-context argument buffers (a context serves one step at a time)
+        q, u_out, valid = self._step_bufs
+        q[0], q[1], q[2] = float(q0[0]), float(q0[1]), float(q0[2])
+        self._check(self.lib.mppi_step(self.h, ctypes.byref(p), q, U.data_ptr(), int(seed), int(step),
                                        u_out, ctypes.byref(valid),
                                        ctypes.byref(D) if D is not None else None))
         return np.array(u_out[:nu], dtype=np.float32), bool(valid.value), out

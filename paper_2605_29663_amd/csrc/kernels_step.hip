@@ -88,7 +88,42 @@ __global__ __launch_bounds__(VAL_SMALL_THREADS) void k_validate_small(
     __shared__ unsigned int skey[MPPI_MAX_T_DEV];
     __shared__ __align__(16) float tile[DMIN_TILE * (MOVING ? 4 : 2)];
     __shared__ float sh[16];
+    // Loads that do not depend on the nominal are issued first, so that
+    // their latency overlaps the nominal re-rollout: the valid count, the
+    // first tile of points (one per thread: VAL_SMALL_THREADS == DMIN_TILE)
+    // and the footprint.
+    static_assert(VAL_SMALL_THREADS == DMIN_TILE, "one point of the first tile per thread");
+    const int nv = *pts.n_valid;
+    const int ti = static_cast<int>(threadIdx.x);
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ti < nv) {
+        p0.x = pts.x[ti];
+        p0.y = pts.y[ti];
+        if (MOVING) {
+            p0.z = pts.vx[ti];
+            p0.w = pts.vy[ti];
+        }
+    }
+    // (polygons above 12 vertices read theirs after the nominal: held
+    // through it, their vertices would push the frame's registers into
+    // scratch)
+    constexpr bool PRE_VERTS = KIND == 0 && PAD <= 12;
+    float2 vtx[KIND == 0 ? PAD : 1];
+    float4 bx[KIND == 1 ? PAD : 1];
+    if constexpr (PRE_VERTS) {
+#pragma unroll
+        for (int k = 0; k < PAD; ++k) vtx[k] = verts[k];
+    } else if constexpr (KIND == 1) {
+#pragma unroll
+        for (int k = 0; k < PAD; ++k) bx[k] = wave_uniform(rects[k]);
+    }
     nominal_block(P, Unew, nom, skey, lds_nom);
+    if (ti < min(nv, DMIN_TILE)) {
+        if (MOVING)
+            reinterpret_cast<float4*>(tile)[ti] = p0;
+        else
+            reinterpret_cast<float2*>(tile)[ti] = make_float2(p0.x, p0.y);
+    }
     __syncthreads();
     const int T = P.T;
     const int S = static_cast<int>(blockDim.x) / T;  // point subsets per pose
@@ -99,15 +134,19 @@ __global__ __launch_bounds__(VAL_SMALL_THREADS) void k_validate_small(
     const float tau = MOVING ? pose_tau(pt, h) : 0.0f;
     float best = INFINITY;
     int besti = -1;
-    const int nv = *pts.n_valid;
     if constexpr (KIND == 0) {
         PolyFrame<PAD> F;
-        F.init(verts, q.z, q.w);
+        if constexpr (PRE_VERTS)
+            F.init_from(vtx, q.z, q.w);
+        else
+            F.init(verts, q.z, q.w);
         for (int t0 = 0; t0 < nv; t0 += DMIN_TILE) {
             const int tn = min(DMIN_TILE, nv - t0);
-            __syncthreads();
-            stage_points<MOVING>(tile, pts, t0, tn);
-            __syncthreads();
+            if (t0 > 0) {
+                __syncthreads();
+                stage_points<MOVING>(tile, pts, t0, tn);
+                __syncthreads();
+            }
             if (act)
                 for (int i = j; i < tn; i += S) {
                     float dx, dy;
@@ -116,14 +155,13 @@ __global__ __launch_bounds__(VAL_SMALL_THREADS) void k_validate_small(
                 }
         }
     } else {
-        float4 bx[PAD];
-#pragma unroll
-        for (int k = 0; k < PAD; ++k) bx[k] = wave_uniform(rects[k]);
         for (int t0 = 0; t0 < nv; t0 += DMIN_TILE) {
             const int tn = min(DMIN_TILE, nv - t0);
-            __syncthreads();
-            stage_points<MOVING>(tile, pts, t0, tn);
-            __syncthreads();
+            if (t0 > 0) {
+                __syncthreads();
+                stage_points<MOVING>(tile, pts, t0, tn);
+                __syncthreads();
+            }
             if (act)
                 for (int i = j; i < tn; i += S) {
                     float dx, dy;

@@ -60,41 +60,60 @@ __device__ __forceinline__ float2 planar_velocity(int model, const float u[3], f
 
 // Serial recursions over n <= ROLL_HCHUNK steps whose per-step inputs sit in
 // LDS at a[k * stride] (k < n): every input is read into a register first,
-// then the fma chain runs and each state is written back over its input.
+// then the fma chain runs and each state is written back over its input.  A
+// full chunk (n == ROLL_HCHUNK) runs straight-line code; a partial one (the
+// horizon's last chunk) a short loop.
 __device__ __forceinline__ float heading_chain(float* a, int stride, int n, float dt, float th) {
-    float w[ROLL_HCHUNK];
+    if (n == ROLL_HCHUNK) {
+        float w[ROLL_HCHUNK];
 #pragma unroll
-    for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = k < n ? a[k * stride] : 0.0f;
+        for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = a[k * stride];
 #pragma unroll
-    for (int k = 0; k < ROLL_HCHUNK; ++k)
-        if (k < n) {
+        for (int k = 0; k < ROLL_HCHUNK; ++k) {
             th = __builtin_fmaf(w[k], dt, th);
             a[k * stride] = th;
         }
+    } else {
+        for (int k = 0; k < n; ++k) {
+            th = __builtin_fmaf(a[k * stride], dt, th);
+            a[k * stride] = th;
+        }
+    }
     return th;
 }
 
 __device__ __forceinline__ void position_chain(float2* a, int stride, int n, float dt, float& x,
                                                float& y) {
-    float2 v[ROLL_HCHUNK];
+    if (n == ROLL_HCHUNK) {
+        float2 v[ROLL_HCHUNK];
 #pragma unroll
-    for (int k = 0; k < ROLL_HCHUNK; ++k) v[k] = k < n ? a[k * stride] : make_float2(0.f, 0.f);
+        for (int k = 0; k < ROLL_HCHUNK; ++k) v[k] = a[k * stride];
 #pragma unroll
-    for (int k = 0; k < ROLL_HCHUNK; ++k)
-        if (k < n) {
+        for (int k = 0; k < ROLL_HCHUNK; ++k) {
             x = __builtin_fmaf(v[k].x, dt, x);
             y = __builtin_fmaf(v[k].y, dt, y);
             a[k * stride] = make_float2(x, y);
         }
+    } else {
+        for (int k = 0; k < n; ++k) {
+            const float2 v = a[k * stride];
+            x = __builtin_fmaf(v.x, dt, x);
+            y = __builtin_fmaf(v.y, dt, y);
+            a[k * stride] = make_float2(x, y);
+        }
+    }
 }
 
 __device__ __forceinline__ float sum_chain(const float* a, int stride, int n, float acc) {
-    float w[ROLL_HCHUNK];
+    if (n == ROLL_HCHUNK) {
+        float w[ROLL_HCHUNK];
 #pragma unroll
-    for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = k < n ? a[k * stride] : 0.0f;
+        for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = a[k * stride];
 #pragma unroll
-    for (int k = 0; k < ROLL_HCHUNK; ++k)
-        if (k < n) acc += w[k];
+        for (int k = 0; k < ROLL_HCHUNK; ++k) acc += w[k];
+    } else {
+        for (int k = 0; k < n; ++k) acc += a[k * stride];
+    }
     return acc;
 }
 
@@ -172,10 +191,12 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
                     u[k] = fminf(v, P.umax[k]);
                 }
             } else if (r < P.K) {
+                float ub[3] = {0.f, 0.f, 0.f};  // issued ahead of the noise arithmetic
+                for (int k = 0; k < nu; ++k) ub[k] = U[h * nu + k];
                 float z[4];
                 normals4(P.seed, P.step, static_cast<uint32_t>(r), static_cast<uint32_t>(h), P.stream, z);
                 for (int k = 0; k < nu; ++k) {
-                    const float base = U[h * nu + k];
+                    const float base = ub[k];
                     float v = base + P.sigma[k] * z[k];
                     v = fmaxf(v, P.umin[k]);
                     v = fminf(v, P.umax[k]);
