@@ -9,11 +9,11 @@ namespace emppi {
 
 namespace {
 
-template <int RB>
-__global__ __launch_bounds__(RB * ROLL_HCHUNK) void k_rollout(StepArgs P, const float* __restrict__ U,
+template <int RB, int HC>
+__global__ __launch_bounds__(RB * HC) void k_rollout(StepArgs P, const float* __restrict__ U,
                                                      RolloutOut o) {
-    __shared__ float lds[roll_lds_floats(RB)];
-    rollout_block<RB>(P, U, o, blockIdx.x * RB, lds);
+    __shared__ float lds[roll_lds_floats(RB, HC)];
+    rollout_block<RB, HC>(P, U, o, blockIdx.x * RB, lds);
 }
 
 __global__ __launch_bounds__(COST_THREADS) void k_cost(StepArgs P,
@@ -236,12 +236,18 @@ hipError_t launch_cost_update(const StepArgs& P, const unsigned int* key,
 
 hipError_t launch_rollout(const StepArgs& P, const float* U, const RolloutOut& o, hipStream_t s) {
     // up to 2^14 rollouts: 16-rollout workgroups (more compute units on the
-    // serial recursions); above, 64-rollout workgroups
-    if (P.Kpad <= (1 << 14))
-        hipLaunchKernelGGL(k_rollout<ROLL_RB_SMALL>, dim3(P.Kpad / ROLL_RB_SMALL),
+    // serial recursions), with the whole horizon in one chunk of 32 steps
+    // when it fits (one noise pass and one pass of each recursion instead of
+    // two); above, 64-rollout workgroups
+    if (P.Kpad <= (1 << 14) && P.T > ROLL_HCHUNK && P.T <= 2 * ROLL_HCHUNK)
+        hipLaunchKernelGGL((k_rollout<ROLL_RB_SMALL, 2 * ROLL_HCHUNK>), dim3(P.Kpad / ROLL_RB_SMALL),
+                           dim3(ROLL_RB_SMALL * 2 * ROLL_HCHUNK), 0, s, P, U, o);
+    else if (P.Kpad <= (1 << 14))
+        hipLaunchKernelGGL((k_rollout<ROLL_RB_SMALL, ROLL_HCHUNK>), dim3(P.Kpad / ROLL_RB_SMALL),
                            dim3(ROLL_RB_SMALL * ROLL_HCHUNK), 0, s, P, U, o);
     else
-        hipLaunchKernelGGL(k_rollout<WAVE>, dim3(P.Kpad / WAVE), dim3(ROLL_THREADS), 0, s, P, U, o);
+        hipLaunchKernelGGL((k_rollout<WAVE, ROLL_HCHUNK>), dim3(P.Kpad / WAVE), dim3(ROLL_THREADS), 0, s,
+                           P, U, o);
     return hipGetLastError();
 }
 

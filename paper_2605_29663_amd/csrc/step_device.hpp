@@ -14,7 +14,7 @@ constexpr int ROLL_THREADS = WAVE * ROLL_HCHUNK;  // one (rollout, step) pair pe
 // LDS of a rollout workgroup of rb rollouts, per (step, rollout) pair: the
 // heading rate / heading / task terms, (cos, sin) of the heading, and the
 // planar velocity / position.
-constexpr int roll_lds_floats(int rb) { return 5 * rb * ROLL_HCHUNK; }
+constexpr int roll_lds_floats(int rb, int hc = ROLL_HCHUNK) { return 5 * rb * hc; }
 constexpr int ROLL_LDS_FLOATS = roll_lds_floats(WAVE);
 // Rollouts per workgroup of the single-scene rollout kernel when K is small:
 // 16 rollouts x 16 steps = 256 threads, four times as many workgroups (and
@@ -58,18 +58,19 @@ __device__ __forceinline__ float2 planar_velocity(int model, const float u[3], f
     }
 }
 
-// Serial recursions over n <= ROLL_HCHUNK steps whose per-step inputs sit in
+// Serial recursions over n <= HC steps whose per-step inputs sit in
 // LDS at a[k * stride] (k < n): every input is read into a register first,
 // then the fma chain runs and each state is written back over its input.  A
-// full chunk (n == ROLL_HCHUNK) runs straight-line code; a partial one (the
+// full chunk (n == HC) runs straight-line code; a partial one (the
 // horizon's last chunk) a short loop.
+template <int HC = ROLL_HCHUNK>
 __device__ __forceinline__ float heading_chain(float* a, int stride, int n, float dt, float th) {
-    if (n == ROLL_HCHUNK) {
-        float w[ROLL_HCHUNK];
+    if (n == HC) {
+        float w[HC];
 #pragma unroll
-        for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = a[k * stride];
+        for (int k = 0; k < HC; ++k) w[k] = a[k * stride];
 #pragma unroll
-        for (int k = 0; k < ROLL_HCHUNK; ++k) {
+        for (int k = 0; k < HC; ++k) {
             th = __builtin_fmaf(w[k], dt, th);
             a[k * stride] = th;
         }
@@ -82,14 +83,15 @@ __device__ __forceinline__ float heading_chain(float* a, int stride, int n, floa
     return th;
 }
 
+template <int HC = ROLL_HCHUNK>
 __device__ __forceinline__ void position_chain(float2* a, int stride, int n, float dt, float& x,
                                                float& y) {
-    if (n == ROLL_HCHUNK) {
-        float2 v[ROLL_HCHUNK];
+    if (n == HC) {
+        float2 v[HC];
 #pragma unroll
-        for (int k = 0; k < ROLL_HCHUNK; ++k) v[k] = a[k * stride];
+        for (int k = 0; k < HC; ++k) v[k] = a[k * stride];
 #pragma unroll
-        for (int k = 0; k < ROLL_HCHUNK; ++k) {
+        for (int k = 0; k < HC; ++k) {
             x = __builtin_fmaf(v[k].x, dt, x);
             y = __builtin_fmaf(v[k].y, dt, y);
             a[k * stride] = make_float2(x, y);
@@ -104,13 +106,14 @@ __device__ __forceinline__ void position_chain(float2* a, int stride, int n, flo
     }
 }
 
+template <int HC = ROLL_HCHUNK>
 __device__ __forceinline__ float sum_chain(const float* a, int stride, int n, float acc) {
-    if (n == ROLL_HCHUNK) {
-        float w[ROLL_HCHUNK];
+    if (n == HC) {
+        float w[HC];
 #pragma unroll
-        for (int k = 0; k < ROLL_HCHUNK; ++k) w[k] = a[k * stride];
+        for (int k = 0; k < HC; ++k) w[k] = a[k * stride];
 #pragma unroll
-        for (int k = 0; k < ROLL_HCHUNK; ++k) acc += w[k];
+        for (int k = 0; k < HC; ++k) acc += w[k];
     } else {
         for (int k = 0; k < n; ++k) acc += a[k * stride];
     }
@@ -150,7 +153,7 @@ __device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py
 }
 
 // Sampling + rollouts of rollouts [r0, r0 + RB) (Algorithm 1 step 1), by
-// chunks of ROLL_HCHUNK horizon steps with RB * ROLL_HCHUNK threads; thread
+// chunks of HC horizon steps with RB * HC threads; thread
 // (step hh, rollout l) keeps its pair's control in registers:
 //   (a) every thread draws the noise of its pair, clamps the sampled control
 //       and evaluates its heading rate;
@@ -162,14 +165,15 @@ __device__ __forceinline__ float task_ctrl(const StepArgs& P, float px, float py
 //   (f) every thread: its pair's scored pose, the distance keys' initial
 //       values and the task + control terms, which the first RB threads then
 //       add up in step order.
-// The result does not depend on RB.  lds: roll_lds_floats(RB) floats.
-template <int RB = WAVE>
+// The result depends on neither RB nor HC.  lds: roll_lds_floats(RB, HC)
+// floats.
+template <int RB = WAVE, int HC = ROLL_HCHUNK>
 __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __restrict__ U,
                                               const RolloutOut& o, int r0, float* lds) {
     const int T = P.T, nu = P.nu, Kpad = P.Kpad;
     float* sw = lds;  // [hh][lane] heading rate, then heading, then task + control terms
-    float2* scs = reinterpret_cast<float2*>(lds + RB * ROLL_HCHUNK);      // [hh][lane] (c, s) after step
-    float2* sxy = reinterpret_cast<float2*>(lds + 3 * RB * ROLL_HCHUNK);  // [hh][lane] velocity, then position after step
+    float2* scs = reinterpret_cast<float2*>(lds + RB * HC);      // [hh][lane] (c, s) after step
+    float2* sxy = reinterpret_cast<float2*>(lds + 3 * RB * HC);  // [hh][lane] velocity, then position after step
     const int lane = threadIdx.x % RB, hh = threadIdx.x / RB;
     const int r = r0 + lane;
     const bool chain = threadIdx.x < RB;  // hh == 0
@@ -177,8 +181,8 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
     // chain threads: the state at the start of the chunk
     float x = P.q0[0], y = P.q0[1], th = P.q0[2], s = 0.f, c = 1.f, jb = 0.0f;
     if (chain) seq_sincos(th, s, c);
-    for (int h0 = 0; h0 < T; h0 += ROLL_HCHUNK) {
-        const int hn = min(ROLL_HCHUNK, T - h0);
+    for (int h0 = 0; h0 < T; h0 += HC) {
+        const int hn = min(HC, T - h0);
         const int h = h0 + hh;
         const bool act = hh < hn;
         float u[3] = {0.f, 0.f, 0.f};
@@ -218,7 +222,7 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
         __syncthreads();
         if (chain) {
             if (rotates) {
-                th = heading_chain(sw + lane, RB, hn, P.dt, th);
+                th = heading_chain<HC>(sw + lane, RB, hn, P.dt, th);
             } else {
                 for (int k = 0; k < hn; ++k) sw[k * RB + lane] = th;
             }
@@ -242,7 +246,7 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
         const float xs = x, ys = y;
         if (chain) {
             if (translates) {
-                position_chain(sxy + lane, RB, hn, P.dt, x, y);
+                position_chain<HC>(sxy + lane, RB, hn, P.dt, x, y);
             } else {
                 for (int k = 0; k < hn; ++k) sxy[k * RB + lane] = make_float2(x, y);
             }
@@ -275,7 +279,7 @@ __device__ __forceinline__ void rollout_block(const StepArgs& P, const float* __
             sw[hh * RB + lane] = task_ctrl(P, pose.x, pose.y, u);
         }
         __syncthreads();
-        if (chain) jb = sum_chain(sw + lane, RB, hn, jb);
+        if (chain) jb = sum_chain<HC>(sw + lane, RB, hn, jb);
         __syncthreads();
     }
     if (chain) o.jbase[r] = jb;
