@@ -234,6 +234,7 @@ def _load_scene(ctx, pkg, prm, sc):
 
 @pytest.mark.parametrize("name,K,N,T,offset", [("c1", None, None, None, 1),
                                                ("c2", 192, 1500, None, 1),
+                                               ("c2", 192, 1500, 10, 1),
                                                ("c3", 128, 2100, 24, 1),
                                                ("c2", 192, 1500, None, 0),
                                                ("c3", 128, 2100, 24, 0)])
@@ -241,7 +242,9 @@ def test_step_parity_small(ctx, pkg, orc, name, K, N, T, offset):
     """Every row of one step against the oracle.  offset = 0 is the literal
     reading of the paper's cost (the (r, h) term scores the pre-step state
     q_h, moving points at time h dt), with static (c2) and moving (c3)
-    points; offset = 1 scores q_{h+1}."""
+    points; offset = 1 scores q_{h+1}.  c2 with T = 10 and c3 validate in
+    one workgroup over two point tiles (T N B <= 2^18, N > 1024), c1 over
+    one."""
     import torch
     prm, sc = _step_case(name, K, N, T)
     prm["state_offset"] = offset
