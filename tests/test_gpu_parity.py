@@ -195,9 +195,13 @@ MODEL_CASES = [("c1", {}), ("c2", {}), ("c3", {}),
                ("c2", dict(state_offset=0))]
 
 
+@pytest.mark.parametrize("T", [33, 24, 7])
 @pytest.mark.parametrize("cfg,over", MODEL_CASES)
-def test_rollout_bit_exact(ctx, pkg, orc, cfg, over):
-    prm = scenes.params(cfg, K=300, T=33, **over)
+def test_rollout_bit_exact(ctx, pkg, orc, cfg, over, T):
+    """Every motion model, bit for bit.  T = 33: chunks of 16 steps (two
+    straight-line chunks and a one-step tail); T = 24: the whole horizon in
+    one 32-step chunk; T = 7: one partial chunk."""
+    prm = scenes.params(cfg, K=300, T=T, **over)
     rng = np.random.default_rng(3)
     lo, hi = np.float32(prm["u_min"]), np.float32(prm["u_max"])
     U = (rng.uniform(size=(prm["T"], prm["nu"])) * (hi - lo) * 0.8 + lo * 0.8).astype(np.float32)
