@@ -167,21 +167,26 @@ int set_footprint(mppi_ctx ctx, int kind, const float* host, int count) {
             pv[2 * b] = host[2 * s];
             pv[2 * b + 1] = host[2 * s + 1];
         }
-        // point-wise tables: (x, y, ex, ey) and (ex/|e|^2, ey/|e|^2, ex/ey, 0)
+        // point-wise tables, per edge taken from its lower end p towards its
+        // upper end with unit direction e and length l: (ex, ey, -(e . p),
+        // e x p) and (l, y of the edge's first vertex, 0, 0)
         std::vector<float> ta(4 * count), tb(4 * count);
         for (int b = 0; b < count; ++b) {
             const int n = (b + 1) % count;
-            const float x = host[2 * b], y = host[2 * b + 1];
-            const float ex = host[2 * n] - x, ey = host[2 * n + 1] - y;
-            const float l2 = std::fma(ex, ex, ey * ey);
-            const float inv = 1.0f / l2;
-            ta[4 * b] = x;
-            ta[4 * b + 1] = y;
-            ta[4 * b + 2] = ex;
-            ta[4 * b + 3] = ey;
-            tb[4 * b] = ex * inv;
-            tb[4 * b + 1] = ey * inv;
-            tb[4 * b + 2] = ey != 0.0f ? ex / ey : 0.0f;
+            const double xa = host[2 * b], ya = host[2 * b + 1];
+            const double xb = host[2 * n], yb = host[2 * n + 1];
+            const bool down = yb < ya;
+            const double px = down ? xb : xa, py = down ? yb : ya;
+            const double dx = (down ? xa : xb) - px, dy = (down ? ya : yb) - py;
+            const double l = std::sqrt(dx * dx + dy * dy);
+            const double ex = l > 0.0 ? dx / l : 0.0, ey = l > 0.0 ? dy / l : 0.0;
+            ta[4 * b] = static_cast<float>(ex);
+            ta[4 * b + 1] = static_cast<float>(ey);
+            ta[4 * b + 2] = static_cast<float>(-(ex * px + ey * py));
+            ta[4 * b + 3] = l > 0.0 ? static_cast<float>(ey * px - ex * py) : 3.0e18f;
+            tb[4 * b] = static_cast<float>(l);
+            tb[4 * b + 1] = host[2 * b + 1];
+            tb[4 * b + 2] = 0.0f;
             tb[4 * b + 3] = 0.0f;
         }
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -127,8 +127,8 @@ __global__ void k_dmin_finalize(const unsigned int* __restrict__ key,
 
 // ---------------------------------------------------------------- point-wise
 // Body-frame query points, one lane each; the footprint table is uniform
-// (scalar loads).  tab_a[b] = (x_b, y_b, ex_b, ey_b), tab_b[b] = (ex_b/|e_b|^2,
-// ey_b/|e_b|^2, ex_b/ey_b, 0) for the polygon; tab_a[j] = box j for rects.
+// (scalar loads).  Polygon: tab_a[b] = (ex, ey, nc, cv) and tab_b[b] = (l,
+// y_b, 0, 0) of edge b (EdgeC); rectangle cover: tab_a[j] = box j.
 __global__ __launch_bounds__(256) void k_sdf_poly_points(const float* __restrict__ px,
                                                          const float* __restrict__ py, int n,
                                                          const float4* __restrict__ ta,
@@ -138,14 +138,14 @@ __global__ __launch_bounds__(256) void k_sdf_poly_points(const float* __restrict
     if (i >= n) return;
     const float x = px[i], y = py[i];
     float4 a = ta[0], b = tb[0];
-    EdgeEval e = edge_eval(x, y, a.x, a.y, a.z, a.w, b.x, b.y, b.z);
+    EdgeEval e = edge_eval(x, y, b.y, a.x, a.y, a.z, a.w, b.x);
     float m = e.d2;
     const bool above0 = e.above;
     bool above = e.above, right = e.right, odd = false;
     for (int k = 1; k < B; ++k) {
         a = ta[k];
         b = tb[k];
-        e = edge_eval(x, y, a.x, a.y, a.z, a.w, b.x, b.y, b.z);
+        e = edge_eval(x, y, b.y, a.x, a.y, a.z, a.w, b.x);
         m = fminf(m, e.d2);
         odd ^= (above != e.above) & right;
         above = e.above;

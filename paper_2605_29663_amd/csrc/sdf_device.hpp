@@ -8,7 +8,7 @@
 //
 // Mapping on gfx950 (wave64, VALU-bound): one lane = one pose (rollout r,
 // horizon h).  The footprint is rotated into the lane's frame once per work
-// item (7 registers per polygon edge); every obstacle point is broadcast to
+// item (6 registers per polygon edge); every obstacle point is broadcast to
 // all lanes from LDS, so the inner loop is pure per-lane VALU work with no
 // cross-lane traffic, and the min over points is a private running minimum.
 // Distances are kept squared and signed, s = sign(d) d^2 (monotone in d), so
@@ -18,29 +18,65 @@
 
 namespace emppi {
 
-__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+// Hardware reciprocal square root (v_rsq_f32, within 1 ulp) of the
+// per-pose edge set-up: it normalises the edge direction and gives the edge
+// length, both of which only scale the along/across coordinates by 1 +
+// O(2^-23); a correctly rounded square root and division cost about 40
+// instructions per edge and work item, against about 11 per edge and point
+// in the loop.
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// One polygon edge against the point (dx, dy) in a frame where the edge runs
-// from (X, Y) to (X + EX, Y + EY): squared point-to-segment distance with the
-// clipped projection t = clamp(w . e / |e|^2, 0, 1) (SX, SY = e / |e|^2), and
-// the ray-casting quantities "vertex above the point" (wy < 0) and "crossing
-// right of the point" (wx < wy * EX / EY, SL = EX / EY).
+// One polygon edge, from (xa, ya) to (xb, yb), taken from its lower end
+// p = (px, py) towards its upper end (a horizontal edge keeps its order):
+// unit direction e, length l, and the offsets that give the point's
+// coordinates along and across the edge in two fused multiply-adds each,
+//   u = e . (d - p) = fma(dx, ex, fma(dy, ey, nc)),   nc = -(e . p),
+//   v = e x (d - p) = fma(dy, ex, fma(dx, -ey, cv)),  cv = ey px - ex py.
+// The clipped projection is clamp(u, 0, l) and the squared point-to-segment
+// distance (u - clamp(u, 0, l))^2 + v^2.  Because the edge points upwards, v
+// > 0 says the point lies left of its line, i.e. a ray from the point towards
+// +x crosses the edge when the edge straddles the point's height: the
+// ray-casting test is the sign of v.  A zero-length edge gets e = 0, l = 0
+// and cv = 3e18, a squared distance of 9e36 that never wins the minimum (its
+// end points are those of the neighbouring edges), and never straddles.
+struct EdgeC {
+    float ex, ey, nc, cv, len;
+};
+
+__device__ __forceinline__ EdgeC edge_setup(float xa, float ya, float xb, float yb) {
+    const bool down = yb < ya;
+    const float px = down ? xb : xa, py = down ? yb : ya;
+    const float qx = down ? xa : xb, qy = down ? ya : yb;
+    const float dx = qx - px, dy = qy - py;
+    const float l2 = __builtin_fmaf(dx, dx, dy * dy);
+    const float r = l2 > 0.0f ? fast_rsq(l2) : 0.0f;
+    EdgeC c;
+    c.ex = dx * r;
+    c.ey = dy * r;
+    c.len = l2 * r;
+    c.nc = -__builtin_fmaf(c.ex, px, c.ey * py);
+    c.cv = l2 > 0.0f ? __builtin_fmaf(c.ey, px, -(c.ex * py)) : 3.0e18f;
+    return c;
+}
+
+// The edge against the point (dx, dy): the squared distance, "the edge's
+// first vertex lies above the point" (y > dy; Y = that vertex's y) and
+// "the edge's line passes right of the point" (v > 0).
 struct EdgeEval {
     float d2;
     bool above;
     bool right;
 };
 
-__device__ __forceinline__ EdgeEval edge_eval(float dx, float dy, float X, float Y, float EX,
-                                              float EY, float SX, float SY, float SL) {
-    const float wx = dx - X, wy = dy - Y;
-    const float t = clamp01(__builtin_fmaf(wy, SY, wx * SX));
-    const float rx = __builtin_fmaf(-t, EX, wx);
-    const float ry = __builtin_fmaf(-t, EY, wy);
+__device__ __forceinline__ EdgeEval edge_eval(float dx, float dy, float Y, float ex, float ey,
+                                              float nc, float cv, float len) {
+    const float u = __builtin_fmaf(dx, ex, __builtin_fmaf(dy, ey, nc));
+    const float v = __builtin_fmaf(dy, ex, __builtin_fmaf(dx, -ey, cv));
+    const float du = u - __builtin_amdgcn_fmed3f(u, 0.0f, len);
     EdgeEval e;
-    e.d2 = __builtin_fmaf(ry, ry, rx * rx);
-    e.above = wy < 0.0f;
-    e.right = wx < wy * SL;
+    e.d2 = __builtin_fmaf(du, du, v * v);
+    e.above = dy < Y;
+    e.right = v > 0.0f;
     return e;
 }
 
@@ -124,21 +160,13 @@ __device__ __forceinline__ void take(float s, int i, float& best, int& besti) {
     }
 }
 
-// Hardware reciprocal (v_rcp_f32, within 1 ulp) of the per-pose edge
-// set-up.  The two quotients there, 1 / |e|^2 of the clipped projection and
-// ex / ey of the crossing test, only scale the projection parameter and
-// place the crossing of a ray that nearly grazes the edge; a correctly
-// rounded division costs about 30 instructions each, 2 per edge and work
-// item, against about 12 per edge and point in the loop.
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
 // Footprint of BP (padded) vertices rotated into the frame of pose q:
-// centred at the pose, aligned with the planning frame.  Padding repeats
-// vertex 0, giving zero-length edges (inverse squared length 0) that never
-// change the min and never straddle the ray.
+// centred at the pose, aligned with the planning frame, 6 registers per
+// edge (the first vertex's y and EdgeC).  Padding repeats vertex 0, giving
+// zero-length edges that never change the min and never straddle the ray.
 template <int BP>
 struct PolyFrame {
-    float X[BP], Y[BP], EX[BP], EY[BP], SX[BP], SY[BP], SL[BP];
+    float Y[BP], EX[BP], EY[BP], NC[BP], CV[BP], LN[BP];
 
     __device__ __forceinline__ void init(const float2* __restrict__ verts, float c, float s) {
         float2 v[BP];
@@ -149,6 +177,7 @@ struct PolyFrame {
 
     // The same from vertices already in registers.
     __device__ __forceinline__ void init_from(const float2 (&v)[BP], float c, float s) {
+        float X[BP];
 #pragma unroll
         for (int b = 0; b < BP; ++b) {
             X[b] = __builtin_fmaf(c, v[b].x, -(s * v[b].y));
@@ -157,25 +186,24 @@ struct PolyFrame {
 #pragma unroll
         for (int b = 0; b < BP; ++b) {
             const int bn = (b + 1) % BP;
-            EX[b] = X[bn] - X[b];
-            EY[b] = Y[bn] - Y[b];
-            const float l2 = __builtin_fmaf(EX[b], EX[b], EY[b] * EY[b]);
-            const float inv = l2 > 0.0f ? fast_rcp(l2) : 0.0f;
-            SX[b] = EX[b] * inv;
-            SY[b] = EY[b] * inv;
-            SL[b] = EY[b] != 0.0f ? EX[b] * fast_rcp(EY[b]) : 0.0f;
+            const EdgeC e = edge_setup(X[b], Y[b], X[bn], Y[bn]);
+            EX[b] = e.ex;
+            EY[b] = e.ey;
+            NC[b] = e.nc;
+            CV[b] = e.cv;
+            LN[b] = e.len;
         }
     }
 
     // sign(d) d^2 of the point (dx, dy), given relative to the pose position.
     __device__ __forceinline__ float eval(float dx, float dy) const {
-        EdgeEval e = edge_eval(dx, dy, X[0], Y[0], EX[0], EY[0], SX[0], SY[0], SL[0]);
+        EdgeEval e = edge_eval(dx, dy, Y[0], EX[0], EY[0], NC[0], CV[0], LN[0]);
         float m = e.d2;
         const bool above0 = e.above;
         bool above = e.above, right = e.right, odd = false;
 #pragma unroll
         for (int b = 1; b < BP; ++b) {
-            e = edge_eval(dx, dy, X[b], Y[b], EX[b], EY[b], SX[b], SY[b], SL[b]);
+            e = edge_eval(dx, dy, Y[b], EX[b], EY[b], NC[b], CV[b], LN[b]);
             m = fminf(m, e.d2);
             odd ^= (above != e.above) & right;
             above = e.above;
@@ -196,10 +224,11 @@ struct PolyFrame {
 template <int HB, int L>
 struct PolyPart {
     static_assert(L == 2 || L == 4, "lane groups of 2 or 4");
-    float X[HB], Y[HB], EX[HB], EY[HB], SX[HB], SY[HB], SL[HB];
+    float Y[HB], EX[HB], EY[HB], NC[HB], CV[HB], LN[HB];
     float Yend;
 
     __device__ __forceinline__ void init(const float2* __restrict__ verts, int b0, float c, float s) {
+        float X[HB];
 #pragma unroll
         for (int b = 0; b < HB; ++b) {
             const float2 v = verts[b0 + b];
@@ -211,15 +240,13 @@ struct PolyPart {
         const float Yn = __builtin_fmaf(s, vn.x, c * vn.y);
 #pragma unroll
         for (int b = 0; b < HB; ++b) {
-            const float nx = b + 1 < HB ? X[b + 1] : Xn;
-            const float ny = b + 1 < HB ? Y[b + 1] : Yn;
-            EX[b] = nx - X[b];
-            EY[b] = ny - Y[b];
-            const float l2 = __builtin_fmaf(EX[b], EX[b], EY[b] * EY[b]);
-            const float inv = l2 > 0.0f ? fast_rcp(l2) : 0.0f;
-            SX[b] = EX[b] * inv;
-            SY[b] = EY[b] * inv;
-            SL[b] = EY[b] != 0.0f ? EX[b] * fast_rcp(EY[b]) : 0.0f;
+            const EdgeC e = edge_setup(X[b], Y[b], b + 1 < HB ? X[b + 1] : Xn,
+                                       b + 1 < HB ? Y[b + 1] : Yn);
+            EX[b] = e.ex;
+            EY[b] = e.ey;
+            NC[b] = e.nc;
+            CV[b] = e.cv;
+            LN[b] = e.len;
         }
         Yend = Yn;
     }
@@ -230,21 +257,21 @@ struct PolyPart {
     // parity runs on the scalar unit on the compare masks; every lane of the
     // wave must be active.
     __device__ __forceinline__ void eval(float dx, float dy, float& m, unsigned long long& odd) const {
-        EdgeEval e = edge_eval(dx, dy, X[0], Y[0], EX[0], EY[0], SX[0], SY[0], SL[0]);
+        EdgeEval e = edge_eval(dx, dy, Y[0], EX[0], EY[0], NC[0], CV[0], LN[0]);
         m = e.d2;
         unsigned long long above = __builtin_amdgcn_ballot_w64(e.above);
         unsigned long long right = __builtin_amdgcn_ballot_w64(e.right);
         odd = 0;
 #pragma unroll
         for (int b = 1; b < HB; ++b) {
-            e = edge_eval(dx, dy, X[b], Y[b], EX[b], EY[b], SX[b], SY[b], SL[b]);
+            e = edge_eval(dx, dy, Y[b], EX[b], EY[b], NC[b], CV[b], LN[b]);
             m = fminf(m, e.d2);
             const unsigned long long ab = __builtin_amdgcn_ballot_w64(e.above);
             odd ^= (above ^ ab) & right;
             above = ab;
             right = __builtin_amdgcn_ballot_w64(e.right);
         }
-        odd ^= (above ^ __builtin_amdgcn_ballot_w64((dy - Yend) < 0.0f)) & right;
+        odd ^= (above ^ __builtin_amdgcn_ballot_w64(dy < Yend)) & right;
     }
 };
 
