@@ -147,6 +147,69 @@ __device__ __forceinline__ void point_rel(const float* lds, int i, float tau, fl
     }
 }
 
+// Two consecutive staged points i, i + 1 (i even) as raw LDS words, one
+// 16-byte read per point pair (static) or per point (moving), so that the
+// next pair's read can be in flight while the current pair is evaluated.
+template <bool MOVING>
+struct PointPair {
+    float4 a, b;  // static: a = (x_i, y_i, x_i+1, y_i+1), b unused
+};
+
+template <bool MOVING>
+__device__ __forceinline__ PointPair<MOVING> load_pair(const float* lds, int i) {
+    const float4* l4 = reinterpret_cast<const float4*>(lds);
+    PointPair<MOVING> p;
+    if (MOVING) {
+        p.a = l4[i];
+        p.b = l4[i + 1];
+    } else {
+        p.a = l4[i >> 1];
+        p.b = p.a;
+    }
+    // keep the read where it is issued (the scheduler would otherwise sink
+    // it next to its first use, leaving its latency exposed)
+    __builtin_amdgcn_sched_barrier(0);
+    return p;
+}
+
+template <bool MOVING>
+__device__ __forceinline__ void pair_rel(const PointPair<MOVING>& p, float tau, float qx, float qy,
+                                         float& dx0, float& dy0, float& dx1, float& dy1) {
+    if (MOVING) {
+        dx0 = __builtin_fmaf(p.a.z, tau, p.a.x) - qx;
+        dy0 = __builtin_fmaf(p.a.w, tau, p.a.y) - qy;
+        dx1 = __builtin_fmaf(p.b.z, tau, p.b.x) - qx;
+        dy1 = __builtin_fmaf(p.b.w, tau, p.b.y) - qy;
+    } else {
+        dx0 = p.a.x - qx;
+        dy0 = p.a.y - qy;
+        dx1 = p.a.z - qx;
+        dy1 = p.a.w - qy;
+    }
+}
+
+// f(pair, i) over the point pairs (i, i + 1) of a staged tile of tn points,
+// i = 0, 2, ...: each pair's LDS read is issued one pair ahead, into two
+// alternating register sets.  Returns the number of points covered (tn
+// rounded down to even).
+template <bool MOVING, typename Fn>
+__device__ __forceinline__ int for_point_pairs(const float* lds, int tn, Fn&& f) {
+    if (tn < 2) return 0;
+    int i = 0;
+    PointPair<MOVING> pa = load_pair<MOVING>(lds, 0);
+    for (; i + 4 <= tn; i += 4) {
+        const PointPair<MOVING> pb = load_pair<MOVING>(lds, i + 2);
+        f(pa, i);
+        pa = load_pair<MOVING>(lds, min(i + 4, tn - 2));
+        f(pb, i + 2);
+    }
+    if (i + 2 <= tn) {
+        f(pa, i);
+        i += 2;
+    }
+    return i;
+}
+
 // Running min (and lowest-index argmin: points arrive in increasing index).
 template <bool ARGMIN>
 __device__ __forceinline__ void take(float s, int i, float& best, int& besti) {
@@ -315,17 +378,17 @@ __device__ __forceinline__ void dmin_poly_range(float4 q, float tau, const Point
         __syncthreads();
         int i = 0;
         // two points per iteration while registers allow (a moving point
-        // holds two more registers until its position at tau is formed)
+        // holds two more registers until its position at tau is formed),
+        // the next pair read from LDS during the current one
         if (BP <= (MOVING ? 14 : 20)) {
-            for (; i + 2 <= tn; i += 2) {
+            i = for_point_pairs<MOVING>(lds, tn, [&](const PointPair<MOVING>& p, int k) {
                 float dx0, dy0, dx1, dy1;
-                point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
-                point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
+                pair_rel<MOVING>(p, tau, q.x, q.y, dx0, dy0, dx1, dy1);
                 const float s0 = F.eval(dx0, dy0);
                 const float s1 = F.eval(dx1, dy1);
-                take<ARGMIN>(s0, t0 + i, best, besti);
-                take<ARGMIN>(s1, t0 + i + 1, best, besti);
-            }
+                take<ARGMIN>(s0, t0 + k, best, besti);
+                take<ARGMIN>(s1, t0 + k + 1, best, besti);
+            });
         }
         for (; i < tn; ++i) {
             float dx, dy;
@@ -351,17 +414,15 @@ __device__ __forceinline__ void dmin_poly_part_range(float4 q, float tau, const 
         __syncthreads();
         stage_points<MOVING>(lds, pts, t0, tn);
         __syncthreads();
-        int i = 0;
-        for (; i + 2 <= tn; i += 2) {
+        const int i = for_point_pairs<MOVING>(lds, tn, [&](const PointPair<MOVING>& p, int k) {
             float dx0, dy0, dx1, dy1, m0, m1;
             unsigned long long o0, o1;
-            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
-            point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
+            pair_rel<MOVING>(p, tau, q.x, q.y, dx0, dy0, dx1, dy1);
             F.eval(dx0, dy0, m0, o0);
             F.eval(dx1, dy1, m1, o1);
-            take<ARGMIN>(part_combine<L>(m0, o0), t0 + i, best, besti);
-            take<ARGMIN>(part_combine<L>(m1, o1), t0 + i + 1, best, besti);
-        }
+            take<ARGMIN>(part_combine<L>(m0, o0), t0 + k, best, besti);
+            take<ARGMIN>(part_combine<L>(m1, o1), t0 + k + 1, best, besti);
+        });
         if (i < tn) {
             float dx, dy, m;
             unsigned long long o;
@@ -396,16 +457,12 @@ __device__ __forceinline__ void dmin_rect_range(float4 q, float tau, const Point
         __syncthreads();
         stage_points<MOVING>(lds, pts, t0, tn);
         __syncthreads();
-        int i = 0;
-        for (; i + 2 <= tn; i += 2) {
+        const int i = for_point_pairs<MOVING>(lds, tn, [&](const PointPair<MOVING>& p, int k) {
             float dx0, dy0, dx1, dy1;
-            point_rel<MOVING>(lds, i, tau, q.x, q.y, dx0, dy0);
-            point_rel<MOVING>(lds, i + 1, tau, q.x, q.y, dx1, dy1);
-            const float s0 = eval(dx0, dy0);
-            const float s1 = eval(dx1, dy1);
-            take<ARGMIN>(s0, t0 + i, best, besti);
-            take<ARGMIN>(s1, t0 + i + 1, best, besti);
-        }
+            pair_rel<MOVING>(p, tau, q.x, q.y, dx0, dy0, dx1, dy1);
+            take<ARGMIN>(eval(dx0, dy0), t0 + k, best, besti);
+            take<ARGMIN>(eval(dx1, dy1), t0 + k + 1, best, besti);
+        });
         if (i < tn) {
             float dx, dy;
             point_rel<MOVING>(lds, i, tau, q.x, q.y, dx, dy);
