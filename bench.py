@@ -49,22 +49,31 @@ VALU_PEAK_TOPS = 157.3 / 2
 #     fma), signed square (fma), min;
 #   5 per (pose, point): transform 3, sign select 1, min over points 1, and
 #     1 more for a moving point (o + v t).
-# The library is built with packed FP32 disabled, so 2-vector adds and fmas
-# issue as two instructions; the same formulas then need
-#   12 per polygon edge and 4 per (pose, point) (the clamp is an output
-#     modifier of the fma, the parity XOR runs on the scalar unit), and
-#   10 per box and 7 per (pose, point) for the rectangle cover,
-# reported as `frac_unpacked_count` beside `frac`.
+# The library evaluates a polygon edge in another algebraic form of the same
+# quantities: the edge is taken from its lower end with a unit direction e
+# and length l, the point's coordinates along and across it are
+# u = e . (p - a) and v = e x (p - a) (2 fmas each, from the point offset and
+# per-edge constants), the clipped projection is med3(u, 0, l), the squared
+# distance (u - med3)^2 + v^2 (sub, mul, fma), and the crossing test is the
+# sign of v.  With packed FP32 disabled that is
+#   10.5 per polygon edge (the above, 2 compares, half of a 3-input min; the
+#     parity XOR runs on the scalar unit) and 4 per (pose, point) (offset 2,
+#     sign select 1, min over points 1);
+#   10 per box and 7 per (pose, point) for the rectangle cover (offset 2,
+#     rotation 4, min over points 1);
+#   2 more per (pose, point) for a moving point (o + v tau),
+# reported as `frac_kernel_count` beside `frac`.
 OPS = {0: (11.0, 5.0), 1: (11.0, 5.0)}
 OPS_MOVING_EXTRA = 1.0
-OPS_UNPACKED = {0: (12.0, 4.0), 1: (10.0, 7.0)}
+OPS_KERNEL = {0: (10.5, 4.0), 1: (10.0, 7.0)}
+OPS_KERNEL_MOVING_EXTRA = {0: 2.0, 1: 2.0}
 
 
-def roofline_ops(kind, pairs, pose_points, moving=False, unpacked=False):
+def roofline_ops(kind, pairs, pose_points, moving=False, kernel_count=False):
     """VALU lane-instructions of one launch of the distance pass."""
-    per_unit, per_pose_point = (OPS_UNPACKED if unpacked else OPS)[kind]
-    if moving and not unpacked:
-        per_pose_point += OPS_MOVING_EXTRA
+    per_unit, per_pose_point = (OPS_KERNEL if kernel_count else OPS)[kind]
+    if moving:
+        per_pose_point += OPS_KERNEL_MOVING_EXTRA[kind] if kernel_count else OPS_MOVING_EXTRA
     return pairs * per_unit + pose_points * per_pose_point
 
 
@@ -438,10 +447,10 @@ def run_batched(args):
     pairs_step = pairs_main + float(np.sum(Ts * Ns * Bs))
     pose_points = float(np.sum(Ks * Ts * Ns))
     ops = roofline_ops(0, pairs_main, pose_points)
-    ops_unpacked = roofline_ops(0, pairs_main, pose_points, unpacked=True)
+    ops_kernel = roofline_ops(0, pairs_main, pose_points, kernel_count=True)
     k_avg = k_ms / max(k_n, 1)
     achieved = ops / (k_avg / 1e3) / 1e12
-    achieved_unpacked = ops_unpacked / (k_avg / 1e3) / 1e12
+    achieved_kernel = ops_kernel / (k_avg / 1e3) / 1e12
     items_main, items_val, _ = b.mppi_batch_info()
     out = {
         "metric": "SDF evals/s (K*T*N*edges per MPPI step) and MPPI step latency",
@@ -459,7 +468,7 @@ def run_batched(args):
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
                      "count": "11 per point-edge pair + 5 per pose-point pair",
-                     "frac_unpacked_count": achieved_unpacked / VALU_PEAK_TOPS,
+                     "frac_kernel_count": achieved_kernel / VALU_PEAK_TOPS,
                      "traffic": traffic_record("c4"), "kernel_ms": k_avg, "launches": k_n,
                      "timing": "HIP events around the persistent launches of eager steps",
                      "tiles": {"pairs_per_item": work, "items_main": items_main,
@@ -629,10 +638,10 @@ def main():
     value = pairs_step / (ms_step / 1e3)
     moving = sc.get("ovx") is not None
     ops_launch = roofline_ops(kind, pairs_main, K * T * N, moving)
-    ops_unpacked = roofline_ops(kind, pairs_main, K * T * N, moving, unpacked=True)
+    ops_kernel = roofline_ops(kind, pairs_main, K * T * N, moving, kernel_count=True)
     k_avg_ms = k_ms / max(k_n, 1)
     achieved = ops_launch / (k_avg_ms / 1e3) / 1e12
-    achieved_unpacked = ops_unpacked / (k_avg_ms / 1e3) / 1e12
+    achieved_kernel = ops_kernel / (k_avg_ms / 1e3) / 1e12
     workload = args.config
 
     out = {
@@ -664,7 +673,7 @@ def main():
                      "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_TOPS,
                      "count": f"11 per point-{'edge' if kind == 0 else 'box'} pair + "
                               f"{5 + (1 if moving else 0)} per pose-point pair",
-                     "frac_unpacked_count": achieved_unpacked / VALU_PEAK_TOPS,
+                     "frac_kernel_count": achieved_kernel / VALU_PEAK_TOPS,
                      "traffic": (None if args.graph or args.polygon_vertices else
                                  traffic_record(workload)),
                      "kernel_ms": k_avg_ms, "launches": k_n,

@@ -339,19 +339,19 @@ struct PolyPart {
 };
 
 // Signed squared distance from a lane group's partial results (lanes
-// L k .. L k + L - 1): the smallest minimum, negative when the group saw an
-// odd number of crossings in total.  The parities combine on the scalar
-// unit (the wave's parity mask XOR the same mask with the bits of each pair
-// swapped; for quads, that result XOR itself with the pairs of each quad
-// swapped); the minima are non-negative, so their integer order is their
-// float order and the partners' values arrive through DPP quad
-// permutations ([1, 0, 3, 2], then [2, 3, 0, 1] for quads) folded into
-// integer mins.  Every lane of the wave must be active.
+// L k .. L k + L - 1), valid in the group's first lane: the smallest
+// minimum, negative when the group saw an odd number of crossings in total.
+// The parities combine on the scalar unit (the wave's parity mask XOR
+// itself shifted down by one lane, and for quads that result XOR itself
+// shifted by two, leaves the group's parity in the bit of its first lane);
+// the minima are non-negative, so their integer order is their float order
+// and the partners' values arrive through DPP quad permutations ([1, 0, 3,
+// 2], then [2, 3, 0, 1] for quads) folded into integer mins.  Every lane of
+// the wave must be active.
 template <int L>
 __device__ __forceinline__ float part_combine(float m, unsigned long long odd) {
-    unsigned long long par =
-        odd ^ (((odd >> 1) & 0x5555555555555555ull) | ((odd << 1) & 0xAAAAAAAAAAAAAAAAull));
-    if (L == 4) par ^= ((par >> 2) & 0x3333333333333333ull) | ((par << 2) & 0xCCCCCCCCCCCCCCCCull);
+    unsigned long long par = odd ^ (odd >> 1);
+    if (L == 4) par ^= par >> 2;
     const bool neg = __builtin_amdgcn_inverse_ballot_w64(par);
     int mi = __float_as_int(m);
     mi = min(mi, __builtin_amdgcn_mov_dpp(mi, 0xB1, 0xF, 0xF, true));
@@ -399,8 +399,9 @@ __device__ __forceinline__ void dmin_poly_range(float4 q, float tau, const Point
 }
 
 // Same with a group of L lanes per pose (L HB padded vertices, see
-// PolyPart); every lane of a group returns the pose's minimum.  Every lane
-// of the workgroup must call it with the same range.
+// PolyPart); the group's first lane returns the pose's minimum (the other
+// lanes' results are not the pose's).  Every lane of the workgroup must call
+// it with the same range.
 template <int HB, int L, bool MOVING, bool ARGMIN = false>
 __device__ __forceinline__ void dmin_poly_part_range(float4 q, float tau, const PointArgs& pts,
                                                      int c0, int c1, const float2* __restrict__ verts,
