@@ -423,31 +423,65 @@ __device__ __forceinline__ void cost_update_block(const StepArgs& P,
     const int lane = threadIdx.x & (WAVE - 1), grp = threadIdx.x / WAVE;
     const int Kpad = P.Kpad;
     const bool first = h == 0;
-    for (int r0 = 0; r0 < Kpad; r0 += WAVE) {
-        const int r = r0 + lane;
-        float J = 0.0f;
-        int chi = 0;
-        if (r < P.K) {
-            for (int hh = grp; hh < P.T; hh += NGRP) {
-                const size_t g = static_cast<size_t>(hh) * Kpad + r;
-                float d;
-                int idx = -1;
-                if (key64) {
-                    const unsigned long long k = key64[g];
-                    d = dkey_distance(static_cast<unsigned int>(k >> 32));
-                    idx = static_cast<int>(static_cast<unsigned int>(k));
-                } else {
-                    d = dkey_distance(key[g]);
-                }
-                const float gap = fmaxf(P.d_safe - d, 0.0f);
-                J += (d < 0.0f ? P.w_coll : 0.0f) + P.w_rep * (gap * gap);
-                chi |= (d < P.d_safe) ? 1 : 0;
-                if (first && diag_dmin) diag_dmin[static_cast<size_t>(r) * P.T + hh] = d;
-                if (first && diag_argmin) diag_argmin[static_cast<size_t>(r) * P.T + hh] = idx;
+    // one rollout's obstacle terms and unsafe flag, term by term in h order
+    auto term = [&](float d, float& J, int& chi) {
+        const float gap = fmaxf(P.d_safe - d, 0.0f);
+        J += (d < 0.0f ? P.w_coll : 0.0f) + P.w_rep * (gap * gap);
+        chi |= (d < P.d_safe) ? 1 : 0;
+    };
+    if (!key64) {
+        // every key this thread decodes (slab s, term i: rollout s 64 + lane,
+        // step grp + 16 i) is read before the first is used, one round trip
+        // to memory instead of one per key; same sums in the same order
+        constexpr int NSLAB = COST_UPDATE_MAX_KPAD / WAVE;
+        constexpr int NTERM = (MPPI_MAX_T_DEV + NGRP - 1) / NGRP;
+        unsigned int kv[NSLAB][NTERM];
+#pragma unroll
+        for (int sl = 0; sl < NSLAB; ++sl)
+#pragma unroll
+            for (int i = 0; i < NTERM; ++i) {
+                const int r = sl * WAVE + lane, hh = grp + i * NGRP;
+                kv[sl][i] = DKEY_INIT;
+                if (sl * WAVE < Kpad && r < P.K && hh < P.T) kv[sl][i] = key[hh * Kpad + r];
             }
+#pragma unroll
+        for (int sl = 0; sl < NSLAB; ++sl) {
+            if (sl * WAVE >= Kpad) break;
+            const int r = sl * WAVE + lane;
+            float J = 0.0f;
+            int chi = 0;
+            if (r < P.K) {
+#pragma unroll
+                for (int i = 0; i < NTERM; ++i) {
+                    const int hh = grp + i * NGRP;
+                    if (hh >= P.T) break;
+                    const float d = dkey_distance(kv[sl][i]);
+                    term(d, J, chi);
+                    if (first && diag_dmin) diag_dmin[static_cast<size_t>(r) * P.T + hh] = d;
+                    if (first && diag_argmin) diag_argmin[static_cast<size_t>(r) * P.T + hh] = -1;
+                }
+            }
+            sP[grp * Kpad + r] = J;
+            sC[grp * Kpad + r] = static_cast<unsigned char>(chi);
         }
-        sP[grp * Kpad + r] = J;
-        sC[grp * Kpad + r] = static_cast<unsigned char>(chi);
+    } else {
+        for (int r0 = 0; r0 < Kpad; r0 += WAVE) {
+            const int r = r0 + lane;
+            float J = 0.0f;
+            int chi = 0;
+            if (r < P.K) {
+                for (int hh = grp; hh < P.T; hh += NGRP) {
+                    const unsigned long long k = key64[static_cast<size_t>(hh) * Kpad + r];
+                    const float d = dkey_distance(static_cast<unsigned int>(k >> 32));
+                    term(d, J, chi);
+                    if (first && diag_dmin) diag_dmin[static_cast<size_t>(r) * P.T + hh] = d;
+                    if (first && diag_argmin)
+                        diag_argmin[static_cast<size_t>(r) * P.T + hh] = static_cast<int>(static_cast<unsigned int>(k));
+                }
+            }
+            sP[grp * Kpad + r] = J;
+            sC[grp * Kpad + r] = static_cast<unsigned char>(chi);
+        }
     }
     __syncthreads();
     for (int r = threadIdx.x; r < Kpad; r += blockDim.x) {
