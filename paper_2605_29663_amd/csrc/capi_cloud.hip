@@ -42,8 +42,7 @@ int cloud_downsample(mppi_ctx ctx, const float* dxyz, int m, const float center[
     HIP_TRY(ctx, ctx->cloud_cell.ensure(sizeof(unsigned long long) * M));
     HIP_TRY(ctx, ctx->cloud_r2.ensure(sizeof(uint32_t) * M));
     HIP_TRY(ctx, ctx->cloud_flag.ensure(sizeof(int) * M));
-    HIP_TRY(ctx, ctx->cloud_excl.ensure(sizeof(int) * M));
-    HIP_TRY(ctx, ctx->cloud_misc.ensure(sizeof(int) * (CLOUD_SCAN_BLOCK + 256 + 8 + 1)));
+    HIP_TRY(ctx, ctx->cloud_misc.ensure(sizeof(int) * (2 * CLOUD_SCAN_BLOCK + 4 * 256 + 8 + 1)));
     CloudArgs a{};
     a.xyz = dxyz;
     a.m = m;
@@ -61,10 +60,9 @@ int cloud_downsample(mppi_ctx ctx, const float* dxyz, int m, const float center[
     w.cell = ctx->cloud_cell.as<unsigned long long>();
     w.r2 = ctx->cloud_r2.as<uint32_t>();
     w.flag = ctx->cloud_flag.as<int>();
-    w.excl = ctx->cloud_excl.as<int>();
-    w.block_sums = ctx->cloud_misc.as<int>();
-    w.hist = w.block_sums + CLOUD_SCAN_BLOCK;
-    w.state = w.hist + 256;
+    w.block_sums = ctx->cloud_misc.as<int2>();
+    w.hist = ctx->cloud_misc.as<int>() + 2 * CLOUD_SCAN_BLOCK;
+    w.state = w.hist + 4 * 256;
     int* d_kept = w.state + 8;
     HIP_TRY(ctx, launch_cloud(a, w, dx, dy, dvalid, d_kept, ctx->stream));
     if (n_kept) {

@@ -23,11 +23,10 @@ struct CloudWork {
     int cap_mask;              // cap - 1 (cap a power of two >= 2 m)
     unsigned long long* cell;  // m: voxel key of each kept point (~0 if dropped)
     uint32_t* r2;              // m: squared range bits
-    int* flag;                 // m
-    int* excl;                 // m: exclusive scan of flag
-    int* block_sums;           // CLOUD_SCAN_BLOCK
-    int* hist;                 // 256
-    int* state;                // 8: select state
+    int* flag;                 // m: point represents its voxel
+    int2* block_sums;          // CLOUD_SCAN_BLOCK: (below, tie) sums per scan block
+    int* hist;                 // 4 x 256: one histogram per radix-select pass
+    int* state;                // 8: representatives, need, threshold, kept
 };
 
 hipError_t launch_cloud(const CloudArgs& a, const CloudWork& w, float* ox, float* oy,

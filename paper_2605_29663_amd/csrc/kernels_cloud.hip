@@ -34,7 +34,7 @@ __global__ void k_cloud_init(CloudWork w) {
         w.keys[s] = CELL_NONE;
         w.first[s] = INT_MAX;
     }
-    if (s < 256) w.hist[s] = 0;
+    if (s < 4 * 256) w.hist[s] = 0;
     if (s < 8) w.state[s] = 0;
 }
 
@@ -91,186 +91,219 @@ __global__ void k_cloud_rep(int m, CloudWork w) {
     if (threadIdx.x == 0 && cnt) atomicAdd(&w.state[0], cnt);
 }
 
-// Histogram of the next 8 bits of the squared-range keys of the
-// representatives that match the bits decided so far (state[2], mask state[3]).
-__global__ void k_cloud_hist(int m, CloudWork w, int shift) {
-    __shared__ int h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t prefix = static_cast<uint32_t>(w.state[2]), mask = static_cast<uint32_t>(w.state[3]);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        const uint32_t u = w.r2[i];
-        if (w.flag[i] && (u & mask) == prefix) atomicAdd(&h[(u >> shift) & 255u], 1);
+// The radix-select state (MSB first, 8 bits per pass) towards the need-th
+// smallest squared-range key of the representatives, need starting at
+// min(representatives, n_out), after `passes` passes: the key prefix, its
+// mask and how many keys are still to be taken among those that match the
+// prefix.  Pass q takes the first bin b of its histogram whose cumulative
+// count reaches need, appends b to the prefix and lowers need by the count
+// before b.  Every workgroup that needs the state derives it from the
+// histograms of the earlier passes (the same integers, so the same state)
+// instead of a separate single-thread launch per pass.  Called by all 64
+// lanes of one wave; every lane returns the state.
+struct CloudSelect {
+    uint32_t prefix, mask;
+    int need;
+};
+
+__device__ CloudSelect cloud_select(const CloudWork& w, int n_out, int passes) {
+    const int lane = static_cast<int>(threadIdx.x) & 63;
+    int c[4][4];  // [pass][bin 4 lane + k]: every histogram read at once
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[q][k] = q < passes ? w.hist[q * 256 + 4 * lane + k] : 0;
+    CloudSelect S{0u, 0u, min(w.state[0], n_out)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= passes || S.need <= 0) break;
+        const int ls = c[q][0] + c[q][1] + c[q][2] + c[q][3];
+        int incl = ls;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        const unsigned long long hit = __ballot(incl >= S.need);
+        if (hit == 0) break;  // not reached: the bins of pass q hold >= need keys
+        const int L = __ffsll(static_cast<long long>(hit)) - 1;
+        int cum = __shfl(incl - ls, L);
+        int b = -1, before = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int ck = __shfl(c[q][k], L);
+            if (b < 0 && cum + ck >= S.need) {
+                b = 4 * L + k;
+                before = cum;
+            }
+            cum += ck;
+        }
+        const int shift = 24 - 8 * q;
+        S.prefix |= static_cast<uint32_t>(b) << shift;
+        S.mask |= 255u << shift;
+        S.need -= before;
     }
-    __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(&w.hist[threadIdx.x], h[threadIdx.x]);
+    return S;
 }
 
-// One radix-select step (MSB first) towards the need-th smallest key:
-// state[1] = how many are still to be taken among the keys that match the
-// prefix.  Clears the histogram for the next pass.
-__global__ void k_cloud_select(CloudWork w, int shift, int first_pass, int n_out) {
+// Histogram (into hist[pass]) of the next 8 bits of the squared-range keys of
+// the representatives that match the prefix the earlier passes decided.
+__global__ __launch_bounds__(256) void k_cloud_hist(int m, CloudWork w, int pass, int n_out) {
+    __shared__ int h[256];
+    __shared__ uint32_t s_prefix, s_mask;
+    __shared__ int s_need;
+    h[threadIdx.x] = 0;
+    if (threadIdx.x < 64) {
+        const CloudSelect S = cloud_select(w, n_out, pass);
+        if (threadIdx.x == 0) {
+            s_prefix = S.prefix;
+            s_mask = S.mask;
+            s_need = S.need;
+        }
+    }
+    __syncthreads();
+    const uint32_t prefix = s_prefix, mask = s_mask;
+    const int shift = 24 - 8 * pass;
+    if (s_need > 0)
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+            const uint32_t u = w.r2[i];
+            if (w.flag[i] && (u & mask) == prefix) atomicAdd(&h[(u >> shift) & 255u], 1);
+        }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&w.hist[pass * 256 + threadIdx.x], h[threadIdx.x]);
+}
+
+// Exclusive prefix sums of (below, tie) count pairs over one workgroup of
+// CLOUD_SCAN_BLOCK threads (every thread must call it); returns the
+// workgroup's totals.
+__device__ int2 block_scan2(int2 v, int2& excl) {
+    __shared__ int2 wsum[CLOUD_SCAN_BLOCK / 64];
+    __shared__ int2 total;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int sx = v.x, sy = v.y;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int tx = __shfl_up(sx, o), ty = __shfl_up(sy, o);
+        if (lane >= o) {
+            sx += tx;
+            sy += ty;
+        }
+    }
+    if (lane == 63) wsum[wid] = make_int2(sx, sy);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        if (first_pass) w.state[1] = min(w.state[0], n_out);
-        int need = w.state[1];
-        if (need > 0) {
-            int cum = 0;
-            for (int b = 0; b < 256; ++b) {
-                const int c = w.hist[b];
-                if (cum + c >= need) {
-                    w.state[2] = static_cast<int>(static_cast<uint32_t>(w.state[2]) |
-                                                  (static_cast<uint32_t>(b) << shift));
-                    w.state[3] = static_cast<int>(static_cast<uint32_t>(w.state[3]) |
-                                                  (255u << shift));
-                    w.state[1] = need - cum;
-                    break;
-                }
-                cum += c;
+        int ax = 0, ay = 0;
+        for (int k = 0; k < CLOUD_SCAN_BLOCK / 64; ++k) {
+            const int2 t = wsum[k];
+            wsum[k] = make_int2(ax, ay);
+            ax += t.x;
+            ay += t.y;
+        }
+        total = make_int2(ax, ay);
+    }
+    __syncthreads();
+    excl = make_int2(wsum[wid].x + sx - v.x, wsum[wid].y + sy - v.y);
+    return total;
+}
+
+// Selection, level 1: the final state (threshold key t = the prefix after 4
+// passes, need) and, per point, below = representative with key < t and tie
+// = representative with key == t (both 0 when nothing is to be taken);
+// exclusive sums of both within each block of CLOUD_SCAN_BLOCK points.
+// Workgroup 0 records t and need in state[2], state[1].
+__global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_cloud_scan1(int m, CloudWork w, int n_out,
+                                                                  int2* __restrict__ excl) {
+    __shared__ uint32_t s_t;
+    __shared__ int s_need;
+    if (threadIdx.x < 64) {
+        const CloudSelect S = cloud_select(w, n_out, 4);
+        if (threadIdx.x == 0) {
+            s_t = S.prefix;
+            s_need = S.need;
+            if (blockIdx.x == 0) {
+                w.state[1] = S.need;
+                w.state[2] = static_cast<int>(S.prefix);
             }
         }
     }
     __syncthreads();
-    w.hist[threadIdx.x] = 0;
+    const int i = blockIdx.x * CLOUD_SCAN_BLOCK + threadIdx.x;
+    int2 v = make_int2(0, 0);
+    if (i < m && s_need > 0 && w.flag[i]) {
+        const uint32_t u = w.r2[i];
+        v = make_int2(u < s_t ? 1 : 0, u == s_t ? 1 : 0);
+    }
+    int2 e;
+    const int2 tot = block_scan2(v, e);
+    if (i < m) excl[i] = e;
+    if (threadIdx.x == 0) w.block_sums[blockIdx.x] = tot;
 }
 
-// tmp = representatives whose key equals the threshold state[2] (ties).
-__global__ void k_cloud_ties(int m, CloudWork w, int* tmp) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    tmp[i] = w.flag[i] && w.r2[i] == static_cast<uint32_t>(w.state[2]) && w.state[1] > 0;
+// Level 2 (one workgroup): exclusive sums of the block totals; the kept count
+// = representatives below t + min(ties, need) goes to state[5].
+__global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_cloud_scan2(int nb, CloudWork w) {
+    const int2 v = static_cast<int>(threadIdx.x) < nb ? w.block_sums[threadIdx.x] : make_int2(0, 0);
+    int2 e;
+    const int2 tot = block_scan2(v, e);
+    if (static_cast<int>(threadIdx.x) < nb) w.block_sums[threadIdx.x] = e;
+    if (threadIdx.x == 0) w.state[5] = tot.x + min(tot.y, max(w.state[1], 0));
 }
 
-// tmp = selected: below the threshold, or a tie among the state[1] of lowest
-// index (excl = rank among the ties).
-__global__ void k_cloud_pick(int m, CloudWork w, int* tmp) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+// Level 3: every representative below t, and the ties of rank < need, go to
+// output slot (representatives below t before it) + min(ties before it,
+// need), i.e. in input order; slots [kept, n_out) are cleared.  Thread g
+// handles point g and output slot g.
+__global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_cloud_scan3(CloudArgs a, CloudWork w,
+                                                                  const int2* __restrict__ excl,
+                                                                  float* ox, float* oy,
+                                                                  unsigned char* valid,
+                                                                  int* n_kept) {
+    const int g = blockIdx.x * CLOUD_SCAN_BLOCK + threadIdx.x;
+    const int kept = w.state[5], need = w.state[1];
     const uint32_t t = static_cast<uint32_t>(w.state[2]);
-    const uint32_t u = w.r2[i];
-    const bool take_any = w.state[0] > 0 && w.state[1] > 0;
-    tmp[i] = w.flag[i] && take_any && (u < t || (u == t && w.excl[i] < w.state[1]));
-}
-
-// Exclusive scan, level 1: per block of CLOUD_SCAN_BLOCK elements.
-__global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_scan_blocks(const int* __restrict__ in, int m,
-                                                                  int* __restrict__ excl,
-                                                                  int* __restrict__ block_sums) {
-    __shared__ int wsum[CLOUD_SCAN_BLOCK / 64];
-    const int i = blockIdx.x * CLOUD_SCAN_BLOCK + threadIdx.x;
-    const int v = i < m ? in[i] : 0;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int s = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(s, o);
-        if (lane >= o) s += t;
-    }
-    if (lane == 63) wsum[wid] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int k = 0; k < CLOUD_SCAN_BLOCK / 64; ++k) {
-            const int t = wsum[k];
-            wsum[k] = acc;
-            acc += t;
+    if (g == 0 && n_kept) *n_kept = kept;
+    if (g < a.m && need > 0 && w.flag[g]) {
+        const uint32_t u = w.r2[g];
+        const int2 e = excl[g], b = w.block_sums[blockIdx.x];
+        const int below = e.x + b.x, ties = e.y + b.y;
+        if (u < t || (u == t && ties < need)) {
+            const int pos = below + min(ties, need);
+            ox[pos] = a.xyz[3 * g];
+            oy[pos] = a.xyz[3 * g + 1];
+            valid[pos] = 1;
         }
-        block_sums[blockIdx.x] = acc;
     }
-    __syncthreads();
-    if (i < m) excl[i] = wsum[wid] + s - v;
-}
-
-// Level 2: exclusive scan of the block sums (one workgroup); total -> *total.
-__global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_scan_top(int* __restrict__ block_sums, int nb,
-                                                               int* __restrict__ total) {
-    __shared__ int wsum[CLOUD_SCAN_BLOCK / 64];
-    const int v = threadIdx.x < nb ? block_sums[threadIdx.x] : 0;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int s = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(s, o);
-        if (lane >= o) s += t;
+    if (g < a.n_out && g >= kept) {
+        ox[g] = 0.0f;
+        oy[g] = 0.0f;
+        valid[g] = 0;
     }
-    if (lane == 63) wsum[wid] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int k = 0; k < CLOUD_SCAN_BLOCK / 64; ++k) {
-            const int t = wsum[k];
-            wsum[k] = acc;
-            acc += t;
-        }
-        if (total) *total = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x < nb) block_sums[threadIdx.x] = wsum[wid] + s - v;
-}
-
-__global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_scan_add(int* __restrict__ excl, int m,
-                                                               const int* __restrict__ block_sums) {
-    const int i = blockIdx.x * CLOUD_SCAN_BLOCK + threadIdx.x;
-    if (i < m) excl[i] += block_sums[blockIdx.x];
-}
-
-__global__ void k_cloud_scatter(CloudArgs a, CloudWork w, const int* __restrict__ tmp, float* ox,
-                                float* oy, unsigned char* valid) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m || !tmp[i]) return;
-    const int pos = w.excl[i];
-    ox[pos] = a.xyz[3 * i];
-    oy[pos] = a.xyz[3 * i + 1];
-    valid[pos] = 1;
-}
-
-__global__ void k_cloud_fill(int n_out, CloudWork w, float* ox, float* oy, unsigned char* valid,
-                             int* n_kept) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int kept = w.state[5];
-    if (j == 0 && n_kept) *n_kept = kept;
-    if (j >= n_out || j < kept) return;
-    ox[j] = 0.0f;
-    oy[j] = 0.0f;
-    valid[j] = 0;
-}
-
-hipError_t scan(const int* in, int m, CloudWork w, int* total, hipStream_t s) {
-    const int nb = (m + CLOUD_SCAN_BLOCK - 1) / CLOUD_SCAN_BLOCK;
-    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(CLOUD_SCAN_BLOCK), 0, s, in, m, w.excl,
-                       w.block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(CLOUD_SCAN_BLOCK), 0, s, w.block_sums, nb, total);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(CLOUD_SCAN_BLOCK), 0, s, w.excl, m, w.block_sums);
-    return hipGetLastError();
 }
 
 }  // namespace
 
-// The whole pre-processing pass on stream s; `tmp` is w.cell reused as an
-// int array once the voxel keys are no longer needed (it holds 2 m ints).
+// The whole pre-processing pass on stream s (10 launches; 2 when m = 0).
+// The (below, tie) prefix sums reuse w.cell (8 bytes per point) once the
+// voxel keys are no longer needed.
 hipError_t launch_cloud(const CloudArgs& a, const CloudWork& w, float* ox, float* oy,
                         unsigned char* valid, int* n_kept, hipStream_t s) {
     const int cap = w.cap_mask + 1;
-    hipLaunchKernelGGL(k_cloud_init, dim3((cap + 255) / 256), dim3(256), 0, s, w);
+    const int n_init = std::max(cap, 4 * 256);  // the table and the four histograms
+    hipLaunchKernelGGL(k_cloud_init, dim3((n_init + 255) / 256), dim3(256), 0, s, w);
     const int m = a.m;
+    int2* excl = reinterpret_cast<int2*>(w.cell);
     if (m > 0) {
         const dim3 g((m + 255) / 256), b(256);
         hipLaunchKernelGGL(k_cloud_insert, g, b, 0, s, a, w);
         hipLaunchKernelGGL(k_cloud_rep, g, b, 0, s, m, w);
         const int hist_blocks = static_cast<int>(std::min<long>((m + 255) / 256, 1024));
-        for (int pass = 0; pass < 4; ++pass) {
-            const int shift = 24 - 8 * pass;
-            hipLaunchKernelGGL(k_cloud_hist, dim3(hist_blocks), dim3(256), 0, s, m, w, shift);
-            hipLaunchKernelGGL(k_cloud_select, dim3(1), dim3(256), 0, s, w, shift, pass == 0 ? 1 : 0,
-                               a.n_out);
-        }
-        int* tmp = reinterpret_cast<int*>(w.cell);
-        hipLaunchKernelGGL(k_cloud_ties, g, b, 0, s, m, w, tmp);
-        if (hipError_t e = scan(tmp, m, w, nullptr, s)) return e;
-        hipLaunchKernelGGL(k_cloud_pick, g, b, 0, s, m, w, tmp);
-        if (hipError_t e = scan(tmp, m, w, w.state + 5, s)) return e;
-        hipLaunchKernelGGL(k_cloud_scatter, g, b, 0, s, a, w, tmp, ox, oy, valid);
+        for (int pass = 0; pass < 4; ++pass)
+            hipLaunchKernelGGL(k_cloud_hist, dim3(hist_blocks), dim3(256), 0, s, m, w, pass, a.n_out);
+        const int nb = (m + CLOUD_SCAN_BLOCK - 1) / CLOUD_SCAN_BLOCK;
+        hipLaunchKernelGGL(k_cloud_scan1, dim3(nb), dim3(CLOUD_SCAN_BLOCK), 0, s, m, w, a.n_out, excl);
+        hipLaunchKernelGGL(k_cloud_scan2, dim3(1), dim3(CLOUD_SCAN_BLOCK), 0, s, nb, w);
     }
-    const int nf = a.n_out > 0 ? a.n_out : 1;
-    hipLaunchKernelGGL(k_cloud_fill, dim3((nf + 255) / 256), dim3(256), 0, s, a.n_out, w, ox, oy,
-                       valid, n_kept);
+    const int n3 = std::max(std::max(m, a.n_out), 1);
+    hipLaunchKernelGGL(k_cloud_scan3, dim3((n3 + CLOUD_SCAN_BLOCK - 1) / CLOUD_SCAN_BLOCK),
+                       dim3(CLOUD_SCAN_BLOCK), 0, s, a, w, excl, ox, oy, valid, n_kept);
     return hipGetLastError();
 }
 
