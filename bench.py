@@ -331,7 +331,7 @@ def run_cloud(args):
                    "voxel": 0.1, "r_max": 10.0, "kept": k},
         "roofline": {"bound": "hbm", "achieved": algo / (ms / 1e3) / 1e9, "peak": 8000.0,
                      "unit": "GB/s", "frac": algo / (ms / 1e3) / 1e9 / 8000.0, "traffic": None,
-                     "note": "algorithmic bytes only; the pass is a chain of 10 small launches"}}))
+                     "note": "algorithmic bytes only; the pass is a chain of 9 small launches"}}))
     ctx.close()
 
 

@@ -21,7 +21,7 @@ struct CloudWork {
     unsigned long long* keys;  // cap: voxel hash table keys
     int* first;                // cap: lowest point index per voxel
     int cap_mask;              // cap - 1 (cap a power of two >= 2 m)
-    unsigned long long* cell;  // m: voxel key of each kept point (~0 if dropped)
+    unsigned long long* cell;  // m: table slot of each kept point (~0 if dropped)
     uint32_t* r2;              // m: squared range bits
     int* flag;                 // m: point represents its voxel
     int2* block_sums;          // CLOUD_SCAN_BLOCK: (below, tie) sums per scan block

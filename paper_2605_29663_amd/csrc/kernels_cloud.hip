@@ -39,7 +39,7 @@ __global__ void k_cloud_init(CloudWork w) {
 }
 
 // Height band, range and finiteness test; voxel insertion (the slot keeps
-// the minimum index of its points).
+// the minimum index of its points); cell[i] = the point's slot, or CELL_NONE.
 __global__ void k_cloud_insert(CloudArgs a, CloudWork w) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.m) return;
@@ -66,29 +66,10 @@ __global__ void k_cloud_insert(CloudArgs a, CloudWork w) {
             }
             slot = (slot + 1) & static_cast<uint32_t>(w.cap_mask);
         }
+        w.cell[i] = slot;
+    } else {
+        w.cell[i] = CELL_NONE;
     }
-    w.cell[i] = key;
-}
-
-// flag[i] = point i represents its voxel; the count goes to state[0].
-__global__ void k_cloud_rep(int m, CloudWork w) {
-    __shared__ int cnt;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    int f = 0;
-    if (i < m) {
-        const unsigned long long key = w.cell[i];
-        if (key != CELL_NONE) {
-            uint32_t slot = mix64(key) & static_cast<uint32_t>(w.cap_mask);
-            while (w.keys[slot] != key) slot = (slot + 1) & static_cast<uint32_t>(w.cap_mask);
-            f = w.first[slot] == i;
-        }
-        w.flag[i] = f;
-    }
-    if (f) atomicAdd(&cnt, 1);
-    __syncthreads();
-    if (threadIdx.x == 0 && cnt) atomicAdd(&w.state[0], cnt);
 }
 
 // The radix-select state (MSB first, 8 bits per pass) towards the need-th
@@ -147,11 +128,34 @@ __device__ CloudSelect cloud_select(const CloudWork& w, int n_out, int passes) {
 
 // Histogram (into hist[pass]) of the next 8 bits of the squared-range keys of
 // the representatives that match the prefix the earlier passes decided.
+// Pass 0 first decides which points represent their voxel (the lowest index
+// of the slot, flag[i]), counts them into state[0] and histograms all of
+// them (its prefix is empty).
 __global__ __launch_bounds__(256) void k_cloud_hist(int m, CloudWork w, int pass, int n_out) {
     __shared__ int h[256];
     __shared__ uint32_t s_prefix, s_mask;
     __shared__ int s_need;
+    __shared__ int cnt;
     h[threadIdx.x] = 0;
+    if (pass == 0) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        int c = 0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+            const unsigned long long slot = w.cell[i];
+            const int f = slot != CELL_NONE && w.first[slot] == i;
+            w.flag[i] = f;
+            if (f) {
+                ++c;
+                atomicAdd(&h[w.r2[i] >> 24], 1);
+            }
+        }
+        if (c) atomicAdd(&cnt, c);
+        __syncthreads();
+        if (threadIdx.x == 0 && cnt) atomicAdd(&w.state[0], cnt);
+        if (h[threadIdx.x]) atomicAdd(&w.hist[threadIdx.x], h[threadIdx.x]);
+        return;
+    }
     if (threadIdx.x < 64) {
         const CloudSelect S = cloud_select(w, n_out, pass);
         if (threadIdx.x == 0) {
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_cloud_scan3(CloudArgs a, C
 
 }  // namespace
 
-// The whole pre-processing pass on stream s (10 launches; 2 when m = 0).
+// The whole pre-processing pass on stream s (9 launches; 2 when m = 0).
 // The (below, tie) prefix sums reuse w.cell (8 bytes per point) once the
 // voxel keys are no longer needed.
 hipError_t launch_cloud(const CloudArgs& a, const CloudWork& w, float* ox, float* oy,
@@ -293,7 +297,6 @@ hipError_t launch_cloud(const CloudArgs& a, const CloudWork& w, float* ox, float
     if (m > 0) {
         const dim3 g((m + 255) / 256), b(256);
         hipLaunchKernelGGL(k_cloud_insert, g, b, 0, s, a, w);
-        hipLaunchKernelGGL(k_cloud_rep, g, b, 0, s, m, w);
         const int hist_blocks = static_cast<int>(std::min<long>((m + 255) / 256, 1024));
         for (int pass = 0; pass < 4; ++pass)
             hipLaunchKernelGGL(k_cloud_hist, dim3(hist_blocks), dim3(256), 0, s, m, w, pass, a.n_out);
