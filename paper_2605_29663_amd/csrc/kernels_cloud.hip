@@ -57,11 +57,18 @@ __global__ void k_cloud_insert(CloudArgs a, CloudWork w) {
               static_cast<uint32_t>(iy + CELL_BIAS);
         uint32_t slot = mix64(key) & static_cast<uint32_t>(w.cap_mask);
         // the table holds at least twice as many slots as points: a free
-        // slot is always reached
+        // slot is always reached.  A slot's key is set once and its index
+        // only decreases, so a plain (relaxed) read that already shows this
+        // key, another key, or an index below i is final, and the atomics
+        // run only when the read leaves the outcome open (most points share
+        // their voxel with many others)
         for (;;) {
-            const unsigned long long prev = atomicCAS(&w.keys[slot], CELL_NONE, key);
-            if (prev == CELL_NONE || prev == key) {
-                atomicMin(&w.first[slot], i);
+            unsigned long long cur =
+                __hip_atomic_load(&w.keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur == CELL_NONE) cur = atomicCAS(&w.keys[slot], CELL_NONE, key);
+            if (cur == CELL_NONE || cur == key) {
+                if (__hip_atomic_load(&w.first[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > i)
+                    atomicMin(&w.first[slot], i);
                 break;
             }
             slot = (slot + 1) & static_cast<uint32_t>(w.cap_mask);
