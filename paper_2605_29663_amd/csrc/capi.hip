@@ -95,7 +95,7 @@ int mppi_destroy(mppi_ctx ctx) {
         DevBuf* bufs[] = {&ctx->poly_verts, &ctx->poly_tab_a, &ctx->poly_tab_b, &ctx->rects,
                           &ctx->px, &ctx->py, &ctx->pvx, &ctx->pvy, &ctx->pidx, &ctx->n_valid,
                           &ctx->path, &ctx->cloud_keys, &ctx->cloud_first, &ctx->cloud_cell,
-                          &ctx->cloud_r2, &ctx->cloud_flag, &ctx->cloud_misc,
+                          &ctx->cloud_r2, &ctx->cloud_misc,
                           &ctx->eps_ws, &ctx->poses_ws, &ctx->jbase, &ctx->jt,
                           &ctx->key, &ctx->key64, &ctx->unew, &ctx->nom_poses,
                           &ctx->key_nom};

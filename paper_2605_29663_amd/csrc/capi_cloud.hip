@@ -41,7 +41,6 @@ int cloud_downsample(mppi_ctx ctx, const float* dxyz, int m, const float center[
     HIP_TRY(ctx, ctx->cloud_first.ensure(sizeof(int) * cap));
     HIP_TRY(ctx, ctx->cloud_cell.ensure(sizeof(unsigned long long) * M));
     HIP_TRY(ctx, ctx->cloud_r2.ensure(sizeof(uint32_t) * M));
-    HIP_TRY(ctx, ctx->cloud_flag.ensure(sizeof(int) * M));
     HIP_TRY(ctx, ctx->cloud_misc.ensure(sizeof(int) * (2 * CLOUD_SCAN_BLOCK + 4 * 256 + 8 + 1)));
     CloudArgs a{};
     a.xyz = dxyz;
@@ -59,7 +58,6 @@ int cloud_downsample(mppi_ctx ctx, const float* dxyz, int m, const float center[
     w.cap_mask = cap - 1;
     w.cell = ctx->cloud_cell.as<unsigned long long>();
     w.r2 = ctx->cloud_r2.as<uint32_t>();
-    w.flag = ctx->cloud_flag.as<int>();
     w.block_sums = ctx->cloud_misc.as<int2>();
     w.hist = ctx->cloud_misc.as<int>() + 2 * CLOUD_SCAN_BLOCK;
     w.state = w.hist + 4 * 256;

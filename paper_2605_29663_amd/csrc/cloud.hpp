@@ -22,8 +22,7 @@ struct CloudWork {
     int* first;                // cap: lowest point index per voxel
     int cap_mask;              // cap - 1 (cap a power of two >= 2 m)
     unsigned long long* cell;  // m: table slot of each kept point (~0 if dropped)
-    uint32_t* r2;              // m: squared range bits
-    int* flag;                 // m: point represents its voxel
+    uint32_t* r2;              // m: squared range bits (KEY_NONE once known not a representative)
     int2* block_sums;          // CLOUD_SCAN_BLOCK: (below, tie) sums per scan block
     int* hist;                 // 4 x 256: one histogram per radix-select pass
     int* state;                // 8: representatives, need, threshold, kept

@@ -90,7 +90,7 @@ struct mppi_ctx_s {
     DevBuf path;
     int n_path = 0;
     // point-cloud pre-processing workspace
-    DevBuf cloud_keys, cloud_first, cloud_cell, cloud_r2, cloud_flag, cloud_misc;
+    DevBuf cloud_keys, cloud_first, cloud_cell, cloud_r2, cloud_misc;
     // step workspaces
     DevBuf eps_ws, poses_ws, jbase, jt, key, key64, unew, nom_poses, key_nom;
     float* h_out = nullptr;  // pinned

@@ -15,6 +15,9 @@ namespace emppi {
 namespace {
 
 constexpr unsigned long long CELL_NONE = ~0ull;
+// key of a point that represents no voxel: above every squared range (the
+// ranges are finite non-negative floats, whose bits stay below 0x7F800000)
+constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;
 constexpr int CELL_BIAS = 1 << 30;  // voxel coordinates are stored biased, never all ones
 
 // MurmurHash3's 64-bit finaliser (Appleby), used to spread voxel keys over
@@ -136,8 +139,10 @@ __device__ CloudSelect cloud_select(const CloudWork& w, int n_out, int passes) {
 // Histogram (into hist[pass]) of the next 8 bits of the squared-range keys of
 // the representatives that match the prefix the earlier passes decided.
 // Pass 0 first decides which points represent their voxel (the lowest index
-// of the slot, flag[i]), counts them into state[0] and histograms all of
-// them (its prefix is empty).
+// of the slot), counts them into state[0], histograms all of them (its
+// prefix is empty) and sets the key of every other point to KEY_NONE, above
+// any squared range, so that later passes and the selection read one word
+// per point.
 __global__ __launch_bounds__(256) void k_cloud_hist(int m, CloudWork w, int pass, int n_out) {
     __shared__ int h[256];
     __shared__ uint32_t s_prefix, s_mask;
@@ -150,11 +155,12 @@ __global__ __launch_bounds__(256) void k_cloud_hist(int m, CloudWork w, int pass
         int c = 0;
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
             const unsigned long long slot = w.cell[i];
-            const int f = slot != CELL_NONE && w.first[slot] == i;
-            w.flag[i] = f;
+            const bool f = slot != CELL_NONE && w.first[slot] == i;
             if (f) {
                 ++c;
                 atomicAdd(&h[w.r2[i] >> 24], 1);
+            } else {
+                w.r2[i] = KEY_NONE;
             }
         }
         if (c) atomicAdd(&cnt, c);
@@ -176,8 +182,8 @@ __global__ __launch_bounds__(256) void k_cloud_hist(int m, CloudWork w, int pass
     const int shift = 24 - 8 * pass;
     if (s_need > 0)
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-            const uint32_t u = w.r2[i];
-            if (w.flag[i] && (u & mask) == prefix) atomicAdd(&h[(u >> shift) & 255u], 1);
+            const uint32_t u = w.r2[i];  // KEY_NONE never matches a prefix of a range key
+            if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & 255u], 1);
         }
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(&w.hist[pass * 256 + threadIdx.x], h[threadIdx.x]);
@@ -238,8 +244,8 @@ __global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_cloud_scan1(int m, CloudWo
     __syncthreads();
     const int i = blockIdx.x * CLOUD_SCAN_BLOCK + threadIdx.x;
     int2 v = make_int2(0, 0);
-    if (i < m && s_need > 0 && w.flag[i]) {
-        const uint32_t u = w.r2[i];
+    if (i < m && s_need > 0) {
+        const uint32_t u = w.r2[i];  // KEY_NONE (not a representative) is above t
         v = make_int2(u < s_t ? 1 : 0, u == s_t ? 1 : 0);
     }
     int2 e;
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(CLOUD_SCAN_BLOCK) void k_cloud_scan3(CloudArgs a, C
     const int kept = w.state[5], need = w.state[1];
     const uint32_t t = static_cast<uint32_t>(w.state[2]);
     if (g == 0 && n_kept) *n_kept = kept;
-    if (g < a.m && need > 0 && w.flag[g]) {
+    if (g < a.m && need > 0) {
         const uint32_t u = w.r2[g];
         const int2 e = excl[g], b = w.block_sums[blockIdx.x];
         const int below = e.x + b.x, ties = e.y + b.y;
