@@ -69,6 +69,31 @@ def test_sdf_polygon_pointwise(ctx, pkg, orc, name):
     assert_sdf_close(d, orc.sdf_polygon(V, P[:, 0], P[:, 1]))
 
 
+@pytest.mark.parametrize("name", ["L8", "towed16", "gapL", "union20", "star32", "star64"])
+def test_sdf_ray_through_vertices(ctx, pkg, orc, name):
+    """Query points at exactly the height of a vertex, and one float step above
+    and below it: the ray-casting corner case, where the half-open rule must
+    count a crossing at a vertex once.  Through the point-wise evaluator and
+    through the fused distance pass (poses with identity rotation around a
+    single point at the origin, so that each pose's offset to the point is
+    the query point exactly and the rotated vertices are the vertices)."""
+    V = POLYS[name].astype(np.float32)
+    y0 = np.unique(V[:, 1])
+    ys = np.unique(np.concatenate([y0, np.nextafter(y0, np.float32(np.inf)),
+                                   np.nextafter(y0, np.float32(-np.inf))])).astype(np.float32)
+    xs = np.linspace(V[:, 0].min() - 1.0, V[:, 0].max() + 1.0, 97).astype(np.float32)
+    xs = np.unique(np.concatenate([xs, V[:, 0]])).astype(np.float32)
+    X, Y = np.meshgrid(xs, ys)
+    P = np.stack([X.ravel(), Y.ravel()], 1).astype(np.float32)
+    ref = orc.sdf_polygon(V.astype(np.float64), P[:, 0].astype(np.float64), P[:, 1].astype(np.float64))
+    ctx.set_footprint(pkg.POLYGON, V)
+    assert_sdf_close(_np(ctx.sdf_polygon(P[:, 0].copy(), P[:, 1].copy())), ref)
+    ctx.set_points(np.zeros(1, np.float32), np.zeros(1, np.float32))
+    poses = np.zeros((len(P), 1, 4), np.float32)
+    poses[:, 0, 0], poses[:, 0, 1], poses[:, 0, 2] = -P[:, 0], -P[:, 1], 1.0
+    assert_sdf_close(_np(ctx.sdf_min_poses(poses))[:, 0], ref)
+
+
 RECTS = {"rects4": scenes.RECTS_4, "gapL": scenes.RECTS_GAP_L, "one": np.array([(0.3, -0.2, 0.5, 0.25)]),
          "L": scenes.SHAPES_LTF["L"][1], "F": scenes.SHAPES_LTF["F"][1],
          "r32": np.concatenate([np.random.default_rng(1).uniform(-1, 1, (32, 2)),
