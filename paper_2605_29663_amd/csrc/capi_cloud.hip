@@ -34,23 +34,8 @@ int cloud_downsample(mppi_ctx ctx, const float* dxyz, int m, const float center[
     if (reach / cp->voxel >= static_cast<double>(1 << 29))
         return fail(ctx, MPPI_E_ARG, "cloud: voxel too small for the range (voxel index >= 2^29)");
     DeviceGuard g(ctx->device);
-    // Hash table of at least twice as many slots as distinct voxels can
-    // occur, so that probing always reaches a free slot: at most one voxel
-    // per point, and at most the voxels of the index box of the kept range.
-    // A kept point lies within r_max (1 + 1e-6) of the centre on each axis
-    // (the float range test errs by a few units in the last place), and the
-    // voxel index is the floor of the correctly rounded quotient, which is
-    // within 2^-22 (|t| + 1) of the exact quotient t.
-    const auto axis_voxels = [&](double c) {
-        const double r = static_cast<double>(cp->r_max) * (1.0 + 1e-6);
-        const double lo = (c - r) / cp->voxel, hi = (c + r) / cp->voxel;
-        const double e = (std::max(std::fabs(lo), std::fabs(hi)) + 1.0) * 0x1p-22;
-        return static_cast<long long>(std::floor(hi + e) - std::floor(lo - e)) + 1;
-    };
-    const long long voxels = std::min(static_cast<long long>(m),
-                                      axis_voxels(center[0]) * axis_voxels(center[1]));
     int cap = 256;
-    while (cap < 2 * voxels) cap <<= 1;
+    while (cap < 2 * m) cap <<= 1;
     const size_t M = static_cast<size_t>(std::max(m, 1));
     HIP_TRY(ctx, ctx->cloud_keys.ensure(sizeof(unsigned long long) * cap));
     HIP_TRY(ctx, ctx->cloud_first.ensure(sizeof(int) * cap));

@@ -20,7 +20,7 @@ struct CloudArgs {
 struct CloudWork {
     unsigned long long* keys;  // cap: voxel hash table keys
     int* first;                // cap: lowest point index per voxel
-    int cap_mask;              // cap - 1 (a power of two >= twice the possible voxels)
+    int cap_mask;              // cap - 1 (cap a power of two >= 2 m)
     unsigned long long* cell;  // m: table slot of each kept point (~0 if dropped)
     uint32_t* r2;              // m: squared range bits (KEY_NONE once known not a representative)
     int2* block_sums;          // CLOUD_SCAN_BLOCK: (below, tie) sums per scan block

@@ -59,8 +59,8 @@ __global__ void k_cloud_insert(CloudArgs a, CloudWork w) {
         key = (static_cast<unsigned long long>(static_cast<uint32_t>(ix + CELL_BIAS)) << 32) |
               static_cast<uint32_t>(iy + CELL_BIAS);
         uint32_t slot = mix64(key) & static_cast<uint32_t>(w.cap_mask);
-        // the table holds at least twice as many slots as distinct voxels
-        // can occur: a free slot is always reached.  A slot's key is set once and its index
+        // the table holds at least twice as many slots as points: a free
+        // slot is always reached.  A slot's key is set once and its index
         // only decreases, so a plain (relaxed) read that already shows this
         // key, another key, or an index below i is final, and the atomics
         // run only when the read leaves the outcome open (most points share
