@@ -73,6 +73,23 @@ def test_cloud_ties_and_degenerate_cases(ctx):
     _check(ctx, pts, (0.0, 0.0), -1, 1, 5.0, 0.5, 3)
 
 
+def test_cloud_voxel_borders_rounding(ctx):
+    """Points on voxel borders and one ulp either side of them, for a voxel
+    that single precision cannot represent (0.1 m), at negative and positive
+    coordinates: the voxel index is the floor of the correctly rounded
+    single-precision quotient on both sides, so the representatives, the
+    kept set and the order match bit for bit."""
+    k = np.arange(-40, 41, dtype=np.float32)
+    b = (k * np.float32(0.1)).astype(np.float32)
+    xs = np.concatenate([b, np.nextafter(b, np.float32(-np.inf)), np.nextafter(b, np.float32(np.inf))])
+    X, Y = np.meshgrid(xs, xs[::7])
+    pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size, np.float32)], 1).astype(np.float32)
+    pts = pts[np.random.default_rng(11).permutation(len(pts))]
+    for n_out in (50, 2000, 100000):
+        k_kept = _check(ctx, pts, (0.05, -0.03), -1, 1, 3.5, 0.1, n_out)
+        assert 0 < k_kept <= n_out
+
+
 def test_cloud_deterministic_and_errors(ctx):
     import torch
     import paper_2605_29663_amd as pkg
